@@ -1,0 +1,577 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU oracle for the pseudopotential
+ * multiple-relaxation-time (MRT) lattice Boltzmann step with the coupled
+ * finite-difference temperature update of
+ *   W. Zhao, B. Xu, Y. Zhang, "Numerical Simulation of Oscillating Multiphase
+ *   Heat Transfer in Parallel Plates using Pseudopotential Multiple-Relaxation-
+ *   Time Lattice Boltzmann Method", arXiv:1803.01756, Section 2 (Eqs. 1-18).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference the GPU path is checked against.  Only the test suite, the
+ * package smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code, header, table or constant with the GPU library: every
+ * constant below is typed here from the paper and every step is written as a
+ * plain loop over the whole field, in the order the algorithm defines, with
+ * no blocking or fusion.
+ *
+ * Readings of silent or garbled passages (each also listed in the design
+ * notes):
+ *  - Eq. 6 equilibrium moments carry 1/rho on the quadratic terms
+ *    (|j|^2/rho etc.); Eq. 8's non-theta terms are exactly the forcing
+ *    derivative of those moments.
+ *  - Eq. 8: the eighth source entry is u_x F_y + u_y F_x and the theta term of
+ *    the third entry enters with a minus sign (mirrors the e/epsilon pair).
+ *  - Eq. 5: denominator rho_l - rho_g, fraction clamped to [0, 1].
+ *  - Eq. 14: the adhesion sum runs over SOLID neighbours with the wall value
+ *    psi_w; the fluid-fluid sum of Eq. 9 runs over fluid neighbours.
+ *  - Eq. 8/9: |F_m|^2 in the theta term is the fluid-fluid force only.
+ *  - Eq. 15 gravity keeps its (rho - rho_v) g form; the oscillating drive of
+ *    the channel runs is a separate uniform acceleration
+ *    rho * g_osc * sin(2 pi n / period) along +x, evaluated at time level n.
+ *  - Eq. 17: classical RK4 weights (h1 + 2 h2 + 2 h3 + h4)/6.  During the
+ *    four stages rho(n), u(n) are frozen; dP/dT is re-evaluated at the
+ *    stage temperature.
+ *  - Eq. 16 space derivatives: isotropic nine-point central differences with
+ *    the same weights as Eq. 9 (w(1)=1/3, w(2)=1/12):
+ *      d_a phi = sum_i w_i e_ia phi(x+e_i),
+ *      lap phi = 2 sum_i w_i (phi(x+e_i) - phi(x)).
+ *    Solid nodes hold T = T_w in every stage and u = 0.
+ *  - lambda and C_v are equal in both phases, so div(lambda grad T) =
+ *    lambda lap T.
+ *  - Order of one step (Fig. 1 is not available): rho -> psi(rho, T(n)) ->
+ *    forces -> u -> tau(rho) -> MRT collision -> T RK4 -> streaming with
+ *    half-way bounce-back.
+ *  - Plates are the solid rows y = 0 and y = Ny-1; the flag PERIODIC_Y
+ *    removes them.
+ */
+#define _USE_MATH_DEFINES
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* flags */
+#define ORC_FREEZE_T 1u     /* skip the temperature update (isothermal)     */
+#define ORC_SINGLE_PHASE 2u /* F_m = 0 and theta term = 0 (ideal gas flow)  */
+#define ORC_PERIODIC_Y 4u   /* no plates: periodic in y as well             */
+
+typedef struct {
+    int32_t Nx, Ny;
+    double a, b, R, omega, Tc;    /* Eq. 11 */
+    double G, theta;              /* Eq. 9-10, Eq. 8 */
+    double Gw, psiw;              /* Eq. 14 */
+    double s_rho, s_e, s_zeta, s_j, s_q; /* Eq. 3 */
+    double tau_g, tau_l, rho_g, rho_l;   /* Eq. 4-5 */
+    double Cv, lambda;            /* Eq. 16 */
+    double T0, Tw;                /* initial fluid / wall temperature */
+    double g_osc, period;         /* oscillating drive along +x */
+    double gx, gy, rho_v;         /* Eq. 15 */
+    uint32_t flags;
+    int32_t pad_;
+} orc_params;
+
+/* ---- D2Q9 lattice, Eq. 2 (velocity index i = 0..8) ---------------------- */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+/* Eq. 9 interaction weights w(|e_i|^2): w(1) = 1/3, w(2) = 1/12 */
+static double wgt(int i) { return i == 0 ? 0.0 : (i <= 4 ? 1.0 / 3.0 : 1.0 / 12.0); }
+
+/* ---- Eq. 6 transformation matrix M, typed from the paper ---------------- */
+static const double MM[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+/* M^-1 by Gauss-Jordan elimination with partial pivoting (no use is made of
+ * the orthogonality of M here; the tests check it separately). */
+static void invert9(const double A[9][9], double Ainv[9][9]) {
+    double W[9][18];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 18; ++c) W[r][c] = c < 9 ? A[r][c] : (c - 9 == r ? 1.0 : 0.0);
+    for (int c = 0; c < 9; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 9; ++r)
+            if (fabs(W[r][c]) > fabs(W[p][c])) p = r;
+        if (p != c)
+            for (int k = 0; k < 18; ++k) { double t = W[c][k]; W[c][k] = W[p][k]; W[p][k] = t; }
+        double d = W[c][c];
+        for (int k = 0; k < 18; ++k) W[c][k] /= d;
+        for (int r = 0; r < 9; ++r) {
+            if (r == c) continue;
+            double m = W[r][c];
+            for (int k = 0; k < 18; ++k) W[r][k] -= m * W[c][k];
+        }
+    }
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) Ainv[r][c] = W[r][c + 9];
+}
+
+static double MINV[9][9];
+static int minv_ready = 0;
+static void ensure_minv(void) {
+    if (!minv_ready) { invert9(MM, MINV); minv_ready = 1; }
+}
+
+void orc_matrix_M(double* out81) { memcpy(out81, MM, sizeof(MM)); }
+void orc_matrix_Minv(double* out81) { ensure_minv(); memcpy(out81, MINV, sizeof(MINV)); }
+
+/* ---- Peng-Robinson equation of state, Eq. 11 ---------------------------- */
+static double kappa_of(double omega) {
+    return 0.37464 + 1.54226 * omega - 0.26992 * omega * omega;
+}
+/* phi(T) = [1 + kappa (1 - sqrt(T/Tc))]^2 */
+double orc_phi(const orc_params* p, double T) {
+    double s = 1.0 + kappa_of(p->omega) * (1.0 - sqrt(T / p->Tc));
+    return s * s;
+}
+/* P_EOS(rho, T) = rho R T / (1 - b rho) - a phi(T) rho^2 / (1 + 2 b rho - b^2 rho^2) */
+double orc_peos(const orc_params* p, double rho, double T) {
+    double b = p->b;
+    return rho * p->R * T / (1.0 - b * rho) -
+           p->a * orc_phi(p, T) * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+}
+/* (dP/drho)_T, derived by hand from Eq. 11 */
+double orc_dpdrho(const orc_params* p, double rho, double T) {
+    double b = p->b, D = 1.0 + 2.0 * b * rho - b * b * rho * rho;
+    return p->R * T / ((1.0 - b * rho) * (1.0 - b * rho)) -
+           2.0 * p->a * orc_phi(p, T) * rho * (1.0 + b * rho) / (D * D);
+}
+/* (dP/dT)_rho: phi'(T) = -kappa [1 + kappa (1 - sqrt(T/Tc))] / sqrt(T Tc) */
+double orc_dpdT(const orc_params* p, double rho, double T) {
+    double b = p->b, k = kappa_of(p->omega);
+    double D = 1.0 + 2.0 * b * rho - b * b * rho * rho;
+    double dphi = -k * (1.0 + k * (1.0 - sqrt(T / p->Tc))) / sqrt(T * p->Tc);
+    return rho * p->R / (1.0 - b * rho) - p->a * dphi * rho * rho / D;
+}
+/* Eq. 10 with c = 1, c_s^2 = 1/3: psi = sqrt(2 (P_EOS - rho/3) / G).  A
+ * negative argument (only possible for very dense liquid) is clamped to 0. */
+double orc_psi(const orc_params* p, double rho, double T) {
+    double arg = 2.0 * (orc_peos(p, rho, T) - rho / 3.0) / p->G;
+    return arg > 0.0 ? sqrt(arg) : 0.0;
+}
+
+/* Critical point of Eq. 11.  At T = Tc the factor phi is 1; on the spinodal
+ * (dP/drho = 0) the temperature is
+ *   T_sp(rho) = 2 a rho (1 + b rho) (1 - b rho)^2 / (R (1 + 2 b rho - b^2 rho^2)^2),
+ * and the critical point is the maximum of that curve.  Golden-section search. */
+static double tsp(double a, double b, double R, double rho) {
+    double D = 1.0 + 2.0 * b * rho - b * b * rho * rho;
+    return 2.0 * a * rho * (1.0 + b * rho) * (1.0 - b * rho) * (1.0 - b * rho) / (R * D * D);
+}
+void orc_critical(double a, double b, double R, double* rho_c, double* T_c) {
+    double lo = 1e-9, hi = 1.0 / b - 1e-9;
+    const double gr = 0.5 * (sqrt(5.0) - 1.0);
+    double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+    double f1 = tsp(a, b, R, x1), f2 = tsp(a, b, R, x2);
+    for (int it = 0; it < 400 && hi - lo > 1e-15 * hi; ++it) {
+        if (f1 < f2) { lo = x1; x1 = x2; f1 = f2; x2 = lo + gr * (hi - lo); f2 = tsp(a, b, R, x2); }
+        else { hi = x2; x2 = x1; f2 = f1; x1 = hi - gr * (hi - lo); f1 = tsp(a, b, R, x1); }
+    }
+    *rho_c = 0.5 * (lo + hi);
+    *T_c = tsp(a, b, R, *rho_c);
+}
+
+/* bisection for a root of g on [lo, hi] with a sign change */
+static double bisect_dpdrho(const orc_params* p, double T, double lo, double hi) {
+    double glo = orc_dpdrho(p, lo, T);
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi), g = orc_dpdrho(p, mid, T);
+        if ((g > 0) == (glo > 0)) { lo = mid; glo = g; } else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+static double bisect_peos(const orc_params* p, double T, double target, double lo, double hi) {
+    double glo = orc_peos(p, lo, T) - target;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi), g = orc_peos(p, mid, T) - target;
+        if ((g > 0) == (glo > 0)) { lo = mid; glo = g; } else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+/* equal-area integral in specific volume v = 1/rho:
+ *   int_{v_l}^{v_g} (P - p) dv = int_{rho_g}^{rho_l} (P(rho) - p) / rho^2 drho
+ *                              = int_{ln rho_g}^{ln rho_l} (P - p) / rho ds,
+ * composite Simpson rule in s = ln rho (the vapour end carries most of the
+ * weight when rho_g is small) */
+static double area(const orc_params* p, double T, double ps, double rg, double rl) {
+    const int n = 40000;
+    double s0 = log(rg), h = (log(rl) - s0) / n, acc = 0.0;
+    for (int k = 0; k <= n; ++k) {
+        double r = exp(s0 + k * h);
+        double v = (orc_peos(p, r, T) - ps) / r;
+        acc += v * (k == 0 || k == n ? 1.0 : (k % 2 ? 4.0 : 2.0));
+    }
+    return acc * h / 3.0;
+}
+/* Maxwell equal-area coexistence at temperature T < Tc.  Returns 0 on
+ * success, -1 if T is not below the critical temperature. */
+int orc_maxwell(const orc_params* p, double T, double* rho_g, double* rho_l, double* p_sat) {
+    double bmax = 1.0 / p->b;
+    /* minimum of dP/drho locates the middle of the unstable branch */
+    double lo = 1e-9, hi = bmax * (1.0 - 1e-9);
+    const double gr = 0.5 * (sqrt(5.0) - 1.0);
+    double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+    double f1 = orc_dpdrho(p, x1, T), f2 = orc_dpdrho(p, x2, T);
+    for (int it = 0; it < 400 && hi - lo > 1e-14 * hi; ++it) {
+        if (f1 > f2) { lo = x1; x1 = x2; f1 = f2; x2 = lo + gr * (hi - lo); f2 = orc_dpdrho(p, x2, T); }
+        else { hi = x2; x2 = x1; f2 = f1; x1 = hi - gr * (hi - lo); f1 = orc_dpdrho(p, x1, T); }
+    }
+    double rm = 0.5 * (lo + hi);
+    if (orc_dpdrho(p, rm, T) >= 0.0) return -1;
+    double rs1 = bisect_dpdrho(p, T, 1e-12, rm);        /* vapour spinodal */
+    double rs2 = bisect_dpdrho(p, T, rm, bmax * (1.0 - 1e-12)); /* liquid spinodal */
+    double pmax = orc_peos(p, rs1, T), pmin = orc_peos(p, rs2, T);
+    double plo = pmin > 0.0 ? pmin : 1e-300, phi_ = pmax;
+    double rg = 0, rl = 0, ps = 0;
+    for (int it = 0; it < 200; ++it) {
+        ps = 0.5 * (plo + phi_);
+        rg = bisect_peos(p, T, ps, 1e-300, rs1);
+        rl = bisect_peos(p, T, ps, rs2, bmax * (1.0 - 1e-15));
+        double A = area(p, T, ps, rg, rl);
+        if (A > 0.0) plo = ps; else phi_ = ps; /* area falls as p rises */
+    }
+    *rho_g = rg; *rho_l = rl; *p_sat = ps;
+    return 0;
+}
+
+/* ---- moments, equilibrium and source, Eqs. 6-8 -------------------------- */
+/* m = M f */
+static void to_moments(const double f[9], double m[9]) {
+    for (int k = 0; k < 9; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < 9; ++i) s += MM[k][i] * f[i];
+        m[k] = s;
+    }
+}
+/* Eq. 6 equilibrium moments with j = rho u (quadratic terms over rho) */
+static void eq_moments(double rho, double jx, double jy, double meq[9]) {
+    double jj = (jx * jx + jy * jy) / rho;
+    meq[0] = rho;
+    meq[1] = -2.0 * rho + 3.0 * jj;
+    meq[2] = rho - 3.0 * jj;
+    meq[3] = jx;
+    meq[4] = -jx;
+    meq[5] = jy;
+    meq[6] = -jy;
+    meq[7] = (jx * jx - jy * jy) / rho;
+    meq[8] = jx * jy / rho;
+}
+
+/* Collision of one node, Eq. 7 then f* = M^-1 m*:
+ *   m* = m - Lambda (m - m_eq) + (I - Lambda/2) S,
+ * with S from Eq. 8 (Li's source with the theta correction).  u is the
+ * half-force velocity of Eq. 13, F the total force, Fm the fluid-fluid part.
+ * tau_v is the viscous relaxation time of Eq. 5 at this node. */
+void orc_collide_node(const orc_params* p, const double f[9], double rho, double ux, double uy,
+                      double Fx, double Fy, double Fmx, double Fmy, double psi, double tau_v,
+                      double fout[9]) {
+    ensure_minv();
+    double s[9] = {p->s_rho, p->s_e, p->s_zeta, p->s_j, p->s_q, p->s_j, p->s_q,
+                   1.0 / tau_v, 1.0 / tau_v};
+    double m[9], meq[9], S[9], ms[9];
+    to_moments(f, m);
+    eq_moments(rho, rho * ux, rho * uy, meq);
+    double uF = ux * Fx + uy * Fy;
+    double th_e = 0.0, th_z = 0.0;
+    if (!(p->flags & ORC_SINGLE_PHASE) && psi > 0.0) {
+        double Fm2 = Fmx * Fmx + Fmy * Fmy;
+        double tau_e = 1.0 / p->s_e, tau_z = 1.0 / p->s_zeta;
+        th_e = 12.0 * p->theta * Fm2 / (psi * psi * (tau_e - 0.5));
+        th_z = 12.0 * p->theta * Fm2 / (psi * psi * (tau_z - 0.5));
+    }
+    S[0] = 0.0;
+    S[1] = 6.0 * uF + th_e;
+    S[2] = -6.0 * uF - th_z;
+    S[3] = Fx;
+    S[4] = -Fx;
+    S[5] = Fy;
+    S[6] = -Fy;
+    S[7] = 2.0 * (ux * Fx - uy * Fy);
+    S[8] = ux * Fy + uy * Fx;
+    for (int k = 0; k < 9; ++k) ms[k] = m[k] - s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * s[k]) * S[k];
+    for (int i = 0; i < 9; ++i) {
+        double v = 0.0;
+        for (int k = 0; k < 9; ++k) v += MINV[i][k] * ms[k];
+        fout[i] = v;
+    }
+}
+
+/* Eq. 5 with the (rho_l - rho_g) denominator and a clamped fraction */
+static double tau_visc(const orc_params* p, double rho) {
+    if (p->rho_l == p->rho_g) return p->tau_g;
+    double fr = (rho - p->rho_g) / (p->rho_l - p->rho_g);
+    if (fr < 0.0) fr = 0.0;
+    if (fr > 1.0) fr = 1.0;
+    return p->tau_g + fr * (p->tau_l - p->tau_g);
+}
+
+/* ---- the simulation ----------------------------------------------------- */
+typedef struct {
+    orc_params p;
+    int64_t n;          /* time level */
+    int64_t psi_clamps; /* nodes where the Eq. 10 argument was clamped */
+    double* f;          /* f_i(x, n) after streaming: [9][Ny][Nx] */
+    double* T;          /* T(x, n): [Ny][Nx], T_w on solid rows */
+    /* scratch, full-field */
+    double *rho, *psi, *ux, *uy, *Fx, *Fy, *Fmx, *Fmy, *fpost;
+    double *Ts, *h, *acc;
+} orc_sim;
+
+static int is_solid(const orc_params* p, int y) {
+    if (p->flags & ORC_PERIODIC_Y) return 0;
+    return y == 0 || y == p->Ny - 1;
+}
+static int wrapx(const orc_params* p, int x) { return (x % p->Nx + p->Nx) % p->Nx; }
+static int wrapy(const orc_params* p, int y) {
+    if (p->flags & ORC_PERIODIC_Y) return (y % p->Ny + p->Ny) % p->Ny;
+    return y; /* fluid rows 1..Ny-2 never reach past rows 0 and Ny-1 */
+}
+#define IDX(p, x, y) ((size_t)(y) * (size_t)(p)->Nx + (size_t)(x))
+#define FIDX(p, i, x, y) (((size_t)(i) * (size_t)(p)->Ny + (size_t)(y)) * (size_t)(p)->Nx + (size_t)(x))
+
+orc_sim* orc_sim_new(const orc_params* p) {
+    if (p->Nx < 1 || p->Ny < 1) return NULL;
+    if (!(p->flags & ORC_PERIODIC_Y) && p->Ny < 3) return NULL;
+    orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
+    s->p = *p;
+    size_t N = (size_t)p->Nx * p->Ny;
+    s->f = (double*)calloc(9 * N, sizeof(double));
+    s->fpost = (double*)calloc(9 * N, sizeof(double));
+    s->T = (double*)calloc(N, sizeof(double));
+    double** fields[] = {&s->rho, &s->psi, &s->ux, &s->uy, &s->Fx, &s->Fy,
+                         &s->Fmx, &s->Fmy, &s->Ts, &s->h, &s->acc};
+    for (size_t k = 0; k < sizeof(fields) / sizeof(fields[0]); ++k)
+        *fields[k] = (double*)calloc(N, sizeof(double));
+    ensure_minv();
+    return s;
+}
+void orc_sim_free(orc_sim* s) {
+    if (!s) return;
+    double* fields[] = {s->f, s->fpost, s->T, s->rho, s->psi, s->ux, s->uy, s->Fx,
+                        s->Fy, s->Fmx, s->Fmy, s->Ts, s->h, s->acc};
+    for (size_t k = 0; k < sizeof(fields) / sizeof(fields[0]); ++k) free(fields[k]);
+    free(s);
+}
+
+/* rest equilibrium f_i = M^-1 m_eq(rho, j = 0) on every fluid node; T = T0
+ * on fluid nodes, T_w on solid rows.  rho0 is an Nx*Ny field indexed
+ * y*Nx + x (solid rows ignored) or NULL for a uniform value rho_uniform. */
+void orc_sim_init(orc_sim* s, const double* rho0, double rho_uniform) {
+    const orc_params* p = &s->p;
+    s->n = 0;
+    s->psi_clamps = 0;
+    for (int y = 0; y < p->Ny; ++y)
+        for (int x = 0; x < p->Nx; ++x) {
+            double meq[9], feq[9];
+            double r = rho0 ? rho0[IDX(p, x, y)] : rho_uniform;
+            eq_moments(r, 0.0, 0.0, meq);
+            for (int i = 0; i < 9; ++i) {
+                double v = 0.0;
+                for (int k = 0; k < 9; ++k) v += MINV[i][k] * meq[k];
+                feq[i] = v;
+            }
+            for (int i = 0; i < 9; ++i) s->f[FIDX(p, i, x, y)] = is_solid(p, y) ? 0.0 : feq[i];
+            s->T[IDX(p, x, y)] = is_solid(p, y) ? p->Tw : p->T0;
+        }
+}
+void orc_sim_set_f(orc_sim* s, const double* f) {
+    memcpy(s->f, f, 9 * sizeof(double) * (size_t)s->p.Nx * s->p.Ny);
+}
+void orc_sim_get_f(const orc_sim* s, double* f) {
+    memcpy(f, s->f, 9 * sizeof(double) * (size_t)s->p.Nx * s->p.Ny);
+}
+void orc_sim_set_T(orc_sim* s, const double* T) {
+    memcpy(s->T, T, sizeof(double) * (size_t)s->p.Nx * s->p.Ny);
+}
+void orc_sim_set_time(orc_sim* s, int64_t n) { s->n = n; }
+int64_t orc_sim_time(const orc_sim* s) { return s->n; }
+int64_t orc_sim_psi_clamps(const orc_sim* s) { return s->psi_clamps; }
+
+/* S1-S4: rho, psi, forces and the half-force velocity at time level n */
+static void macroscopic(orc_sim* s) {
+    const orc_params* p = &s->p;
+    const int Nx = p->Nx, Ny = p->Ny;
+    /* S1 (Eq. 13) and S2 (Eq. 10-11) */
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            size_t c = IDX(p, x, y);
+            if (is_solid(p, y)) { s->rho[c] = 0.0; s->psi[c] = p->psiw; continue; }
+            double r = 0.0;
+            for (int i = 0; i < 9; ++i) r += s->f[FIDX(p, i, x, y)];
+            s->rho[c] = r;
+            double arg = 2.0 * (orc_peos(p, r, s->T[c]) - r / 3.0) / p->G;
+            if (!(arg > 0.0)) s->psi_clamps++;
+            s->psi[c] = orc_psi(p, r, s->T[c]);
+        }
+    /* S3: Eq. 9 (fluid neighbours), Eq. 14 (solid neighbours), Eq. 15 and
+     * the oscillating drive; S4: Eq. 13 velocity */
+    double drive = 0.0;
+    if (p->period > 0.0) drive = p->g_osc * sin(2.0 * 3.14159265358979323846 * (double)s->n / p->period);
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            size_t c = IDX(p, x, y);
+            if (is_solid(p, y)) {
+                s->ux[c] = s->uy[c] = s->Fx[c] = s->Fy[c] = s->Fmx[c] = s->Fmy[c] = 0.0;
+                continue;
+            }
+            double sfx = 0.0, sfy = 0.0, swx = 0.0, swy = 0.0;
+            for (int i = 1; i < 9; ++i) {
+                int xn = wrapx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
+                if (is_solid(p, yn)) {
+                    swx += wgt(i) * EX[i];
+                    swy += wgt(i) * EY[i];
+                } else {
+                    double pn = s->psi[IDX(p, xn, yn)];
+                    sfx += wgt(i) * pn * EX[i];
+                    sfy += wgt(i) * pn * EY[i];
+                }
+            }
+            double Fmx = 0.0, Fmy = 0.0;
+            if (!(p->flags & ORC_SINGLE_PHASE)) {
+                Fmx = -p->G * s->psi[c] * sfx;
+                Fmy = -p->G * s->psi[c] * sfy;
+            }
+            double Fax = -p->Gw * s->psi[c] * p->psiw * swx;
+            double Fay = -p->Gw * s->psi[c] * p->psiw * swy;
+            double r = s->rho[c];
+            double Fbx = r * drive + (r - p->rho_v) * p->gx;
+            double Fby = (r - p->rho_v) * p->gy;
+            s->Fmx[c] = Fmx;
+            s->Fmy[c] = Fmy;
+            s->Fx[c] = Fmx + Fax + Fbx;
+            s->Fy[c] = Fmy + Fay + Fby;
+            double jx = 0.0, jy = 0.0;
+            for (int i = 0; i < 9; ++i) {
+                jx += EX[i] * s->f[FIDX(p, i, x, y)];
+                jy += EY[i] * s->f[FIDX(p, i, x, y)];
+            }
+            s->ux[c] = (jx + 0.5 * s->Fx[c]) / r;
+            s->uy[c] = (jy + 0.5 * s->Fy[c]) / r;
+        }
+}
+
+/* K(T) of Eq. 16 at every fluid node for the stage field Ts (T_w on solid
+ * rows), with rho and u frozen at time level n. */
+static void heat_rhs(const orc_sim* s, const double* Ts, double* out) {
+    const orc_params* p = &s->p;
+    for (int y = 0; y < p->Ny; ++y)
+        for (int x = 0; x < p->Nx; ++x) {
+            size_t c = IDX(p, x, y);
+            if (is_solid(p, y)) { out[c] = 0.0; continue; }
+            double tx = 0.0, ty = 0.0, lap = 0.0, div = 0.0;
+            for (int i = 1; i < 9; ++i) {
+                int xn = wrapx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
+                size_t cn = IDX(p, xn, yn);
+                double w = wgt(i);
+                tx += w * EX[i] * Ts[cn];
+                ty += w * EY[i] * Ts[cn];
+                lap += 2.0 * w * (Ts[cn] - Ts[c]);
+                double uxn = is_solid(p, yn) ? 0.0 : s->ux[cn];
+                double uyn = is_solid(p, yn) ? 0.0 : s->uy[cn];
+                div += w * (EX[i] * uxn + EY[i] * uyn);
+            }
+            double r = s->rho[c], T = Ts[c];
+            out[c] = -(s->ux[c] * tx + s->uy[c] * ty) + p->lambda / (r * p->Cv) * lap -
+                     T / (r * p->Cv) * orc_dpdT(p, r, T) * div;
+        }
+}
+
+/* exported for unit tests: K(T) for user-given fields (Nx*Ny each; rho and u
+ * ignored on solid rows) */
+void orc_heat_rhs(const orc_params* p, const double* rho, const double* ux, const double* uy,
+                  const double* T, double* out) {
+    orc_sim tmp;
+    memset(&tmp, 0, sizeof(tmp));
+    tmp.p = *p;
+    tmp.rho = (double*)rho;
+    tmp.ux = (double*)ux;
+    tmp.uy = (double*)uy;
+    heat_rhs(&tmp, T, out);
+}
+
+/* one full step n -> n+1 (S1-S9) */
+static void step_once(orc_sim* s) {
+    const orc_params* p = &s->p;
+    const int Nx = p->Nx, Ny = p->Ny;
+    const size_t N = (size_t)Nx * Ny;
+    macroscopic(s);
+    /* S5-S6: collision on every fluid node into fpost */
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            if (is_solid(p, y)) continue;
+            size_t c = IDX(p, x, y);
+            double f[9], fo[9];
+            for (int i = 0; i < 9; ++i) f[i] = s->f[FIDX(p, i, x, y)];
+            orc_collide_node(p, f, s->rho[c], s->ux[c], s->uy[c], s->Fx[c], s->Fy[c], s->Fmx[c],
+                             s->Fmy[c], s->psi[c], tau_visc(p, s->rho[c]), fo);
+            for (int i = 0; i < 9; ++i) s->fpost[FIDX(p, i, x, y)] = fo[i];
+        }
+    /* S7: classical RK4 for T (Eqs. 16-18) with rho(n), u(n) frozen */
+    if (!(p->flags & ORC_FREEZE_T)) {
+        const double cst[4] = {0.5, 0.5, 1.0, 0.0}; /* stage offsets */
+        const double wts[4] = {1.0, 2.0, 2.0, 1.0};
+        memcpy(s->Ts, s->T, N * sizeof(double));
+        for (size_t c = 0; c < N; ++c) s->acc[c] = 0.0;
+        for (int st = 0; st < 4; ++st) {
+            heat_rhs(s, s->Ts, s->h);
+            for (int y = 0; y < Ny; ++y)
+                for (int x = 0; x < Nx; ++x) {
+                    size_t c = IDX(p, x, y);
+                    if (is_solid(p, y)) continue;
+                    s->acc[c] += wts[st] * s->h[c];
+                }
+            for (int y = 0; y < Ny; ++y)
+                for (int x = 0; x < Nx; ++x) {
+                    size_t c = IDX(p, x, y);
+                    if (is_solid(p, y)) continue;
+                    s->Ts[c] = s->T[c] + cst[st] * s->h[c];
+                }
+        }
+        for (int y = 0; y < Ny; ++y)
+            for (int x = 0; x < Nx; ++x) {
+                size_t c = IDX(p, x, y);
+                if (!is_solid(p, y)) s->T[c] += s->acc[c] / 6.0;
+            }
+    }
+    /* S8: streaming (Eq. 12) with half-way bounce-back at solid nodes */
+    for (size_t k = 0; k < 9 * N; ++k) s->f[k] = 0.0;
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            if (is_solid(p, y)) continue;
+            for (int i = 0; i < 9; ++i) {
+                int xn = wrapx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
+                double v = s->fpost[FIDX(p, i, x, y)];
+                if (is_solid(p, yn)) s->f[FIDX(p, OPP[i], x, y)] = v;
+                else s->f[FIDX(p, i, xn, yn)] = v;
+            }
+        }
+    s->n += 1; /* S9 */
+}
+
+void orc_sim_step(orc_sim* s, int64_t nsteps) {
+    for (int64_t k = 0; k < nsteps; ++k) step_once(s);
+}
+
+/* rho, u (half-force, Eq. 13) and T at the current time level; also the
+ * force fields.  Any output pointer may be NULL.  Solid rows give rho = 0,
+ * u = 0, T = T_w. */
+void orc_sim_moments(orc_sim* s, double* rho, double* ux, double* uy, double* T, double* Fx,
+                     double* Fy) {
+    int64_t save = s->psi_clamps;
+    macroscopic(s);
+    s->psi_clamps = save;
+    size_t N = (size_t)s->p.Nx * s->p.Ny;
+    if (rho) memcpy(rho, s->rho, N * sizeof(double));
+    if (ux) memcpy(ux, s->ux, N * sizeof(double));
+    if (uy) memcpy(uy, s->uy, N * sizeof(double));
+    if (T) memcpy(T, s->T, N * sizeof(double));
+    if (Fx) memcpy(Fx, s->Fx, N * sizeof(double));
+    if (Fy) memcpy(Fy, s->Fy, N * sizeof(double));
+}

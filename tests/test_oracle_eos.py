@@ -1,0 +1,113 @@
+"""Pins of the oracle's thermodynamics (arXiv:1803.01756 Eqs. 10-11).
+
+* Critical point: dP/drho and d2P/drho2 (central differences of the
+  oracle's P_EOS, not its hand-derived derivative) vanish at the oracle's
+  (rho_c, Tc), and Tc equals the textbook Peng-Robinson relation
+  Tc = Omega_b a / (Omega_a b R) with the Omega constants the paper prints.
+* Coexistence: the Maxwell densities at 0.86 Tc round to the values the
+  paper prints in Sec. 3.1 (golden fixture), pressures match at both
+  densities, and scipy's adaptive quadrature confirms the equal-area rule.
+* (dP/dT)_rho against central differences in T; psi from Eq. 10 against the
+  pressure decomposition P = rho c_s^2 + G psi^2 / 2.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+def test_critical_point(orc):
+    c = _gold("paper_eos_constants.json")
+    rc, tc = orc.critical(c["a"], c["b"], c["R"])
+    p = orc.default_params(Tc=tc)
+    h = 1e-3
+    d1 = (orc.peos(p, rc + h, tc) - orc.peos(p, rc - h, tc)) / (2 * h)
+    d2 = (orc.peos(p, rc + h, tc) - 2 * orc.peos(p, rc, tc) + orc.peos(p, rc - h, tc)) / h ** 2
+    assert abs(d1) < 1e-8 and abs(d2) < 1e-6
+    textbook = c["Omega_b"] * c["a"] / (c["Omega_a"] * c["b"] * c["R"])
+    # the printed Omega_b = 0.0778 carries three digits (+-6e-4 relative)
+    assert abs(tc / textbook - 1) < 2e-4
+    # the printed 0.1096 is 0.2 % above the critical point of Eq. 11 itself
+    assert 0.001 < c["Tc_printed"] / tc - 1 < 0.003
+    # Peng-Robinson: b rho_c = Omega_b / Z_c with Z_c = 0.3074
+    assert abs(c["b"] * rc - 0.0778 / 0.3074) < 2e-4
+
+
+def test_maxwell_matches_printed_coexistence(orc):
+    g = _gold("paper_coexistence.json")
+    p = orc.default_params()
+    rg, rl, ps = orc.maxwell(p, g["T_over_Tc"] * p.Tc)
+    assert round(rl, 1) == g["rho_l"]
+    assert round(rg, 2) == g["rho_g"]
+    T = p.T0
+    assert abs(orc.peos(p, rg, T) / ps - 1) < 1e-10
+    assert abs(orc.peos(p, rl, T) / ps - 1) < 1e-10
+    area, _ = integrate.quad(lambda r: (orc.peos(p, r, T) - ps) / r ** 2, rg, rl,
+                             epsabs=1e-14, epsrel=1e-12, limit=200)
+    # equal areas in the (v, P) plane: the signed area vanishes
+    scale, _ = integrate.quad(lambda r: abs(orc.peos(p, r, T) - ps) / r ** 2, rg, rl,
+                              limit=200)
+    assert abs(area) < 1e-9 * scale
+
+
+@pytest.mark.parametrize("frac", [0.56, 0.65, 0.78, 0.86, 0.9])
+def test_maxwell_equal_chemical_potential(orc, frac):
+    """Equal area <=> equal chemical potential:
+    int_{rho_g}^{rho_l} (dP/drho) / rho drho = 0, with scipy's quadrature."""
+    p = orc.default_params()
+    T = frac * p.Tc
+    rg, rl, ps = orc.maxwell(p, T)
+    assert rg < rl
+    pts = [2 * rg, 1.0, 3.0]
+    dmu, _ = integrate.quad(lambda r: orc.dpdrho(p, r, T) / r, rg, rl, limit=400,
+                            epsrel=1e-12, points=pts)
+    scale, _ = integrate.quad(lambda r: abs(orc.dpdrho(p, r, T)) / r, rg, rl, limit=400,
+                              points=pts)
+    assert abs(dmu) < 1e-9 * scale
+
+
+def test_dpdT_matches_finite_difference(orc):
+    p = orc.default_params()
+    for rho in (0.2, 0.38, 2.6, 6.5, 8.0):
+        for frac in (0.56, 0.8, 0.86, 1.0):
+            T = frac * p.Tc
+            h = 1e-6 * T
+            fd = (orc.peos(p, rho, T + h) - orc.peos(p, rho, T - h)) / (2 * h)
+            assert abs(orc.dpdT(p, rho, T) - fd) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_dpdrho_matches_finite_difference(orc):
+    p = orc.default_params()
+    for rho in (0.2, 2.6, 6.5):
+        T = 0.8 * p.Tc
+        h = 1e-6
+        fd = (orc.peos(p, rho + h, T) - orc.peos(p, rho - h, T)) / (2 * h)
+        assert abs(orc.dpdrho(p, rho, T) - fd) < 1e-7
+
+
+def test_psi_reproduces_eos_pressure(orc):
+    """Eq. 10 inverted: rho/3 + G psi^2 / 2 = P_EOS wherever psi > 0."""
+    p = orc.default_params()
+    for rho in np.linspace(0.05, 8.5, 40):
+        for frac in (0.56, 0.86, 1.1):
+            T = frac * p.Tc
+            ps = orc.psi(p, rho, T)
+            if ps > 0:
+                assert abs(rho / 3 + p.G * ps ** 2 / 2 - orc.peos(p, rho, T)) < 1e-13 * (1 + rho)
+
+
+def test_psi_clamps_only_past_dense_limit(orc):
+    """The Eq. 10 argument first turns negative near rho ~ 8.97 at 0.86 Tc."""
+    p = orc.default_params()
+    T = p.T0
+    assert orc.psi(p, 8.9, T) > 0
+    assert orc.psi(p, 9.05, T) == 0.0

@@ -1,0 +1,128 @@
+"""Pins of the oracle's temperature update (arXiv:1803.01756 Eqs. 16-18).
+
+* K(T) on polynomial fields where the nine-point stencils are exact: the
+  advection term on a linear T, the conduction term on a quadratic T and the
+  compression term on a linear velocity field, with (dP/dT)_rho taken from
+  central differences of P_EOS.
+* The full coupled step on Fourier modes of T in a periodic box at rest (and
+  in uniform motion): the stencils map exp(ikx) to i sin(k) (gradient) and
+  2 (cos k - 1) (Laplacian), so classical RK4 multiplies the mode by
+  R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 per step, exactly up to rounding.
+  The printed weights (h1 + h2 + h3 + h4)/6 of Eq. 17 would give
+  1 + 2z/3 + ... and fail.
+"""
+import numpy as np
+import pytest
+
+E = np.array([(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1),
+              (1, 1), (-1, 1), (-1, -1), (1, -1)], dtype=float)
+W_EQ = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def _grid(Nx, Ny):
+    y, x = np.mgrid[0:Ny, 0:Nx].astype(float)
+    return x, y
+
+
+def test_advection_term_exact_on_linear_field(orc):
+    Nx, Ny = 9, 7
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y, lam=0.0)
+    x, y = _grid(Nx, Ny)
+    rng = np.random.default_rng(0)
+    rho = rng.uniform(0.3, 6.0, (Ny, Nx))
+    ux, uy = np.full((Ny, Nx), 0.03), np.full((Ny, Nx), -0.02)
+    T = p.T0 + 1e-3 * x - 2e-3 * y
+    K = orc.heat_rhs(p, rho, ux, uy, T)
+    inner = (slice(1, -1), slice(1, -1))
+    np.testing.assert_allclose(K[inner], -(0.03 * 1e-3 + 0.02 * 2e-3), rtol=1e-12)
+
+
+def test_conduction_term_exact_on_quadratic_field(orc):
+    Nx, Ny = 9, 7
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y, lam=0.37, Cv=4.0)
+    x, y = _grid(Nx, Ny)
+    rng = np.random.default_rng(1)
+    rho = rng.uniform(0.3, 6.0, (Ny, Nx))
+    zero = np.zeros((Ny, Nx))
+    T = p.T0 + 1e-4 * (3 * x ** 2 - 2 * x * y + 5 * y ** 2 + x)
+    K = orc.heat_rhs(p, rho, zero, zero, T)
+    lapT = 1e-4 * (6 + 10)
+    inner = (slice(1, -1), slice(1, -1))
+    np.testing.assert_allclose(K[inner], (0.37 / (rho * 4.0) * lapT)[inner], rtol=1e-10)
+
+
+def test_compression_term_on_linear_velocity(orc):
+    Nx, Ny = 9, 7
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y)
+    x, y = _grid(Nx, Ny)
+    rng = np.random.default_rng(2)
+    rho = rng.uniform(0.3, 6.0, (Ny, Nx))
+    ux = 1e-3 * (2 * x - y)
+    uy = 1e-3 * (x + 3 * y)
+    T = np.full((Ny, Nx), p.T0)
+    K = orc.heat_rhs(p, rho, ux, uy, T)
+    div = 1e-3 * (2 + 3)
+    h = 1e-6 * p.T0
+    inner = (slice(1, -1), slice(1, -1))
+    for j in range(1, Ny - 1):
+        for i in range(1, Nx - 1):
+            r = rho[j, i]
+            dpdT = (orc.peos(p, r, p.T0 + h) - orc.peos(p, r, p.T0 - h)) / (2 * h)
+            expect = -p.T0 / (r * p.Cv) * dpdT * div
+            assert abs(K[j, i] - expect) < 1e-8 * abs(expect)
+    assert np.isfinite(K[inner]).all()
+
+
+def test_walls_hold_dirichlet_temperature(orc):
+    """Solid rows keep T_w through a step; a fluid at T_w next to the wall at
+    rest stays at T_w (K = 0)."""
+    Nx, Ny = 8, 6
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.SINGLE_PHASE, period=0.0,
+                           T0=0.8 * orc.critical()[1], Tw=0.8 * orc.critical()[1])
+    s = orc.Sim(p, rho_uniform=0.5)
+    s.step(5)
+    T = s.moments()[3]
+    np.testing.assert_allclose(T, p.Tw, rtol=1e-14)
+
+
+def _rk4_factor(z):
+    return 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+
+
+@pytest.mark.parametrize("mode,rho", [(1, 0.38), (3, 1.0), (5, 6.5)])
+def test_rk4_conduction_mode_decay(orc, mode, rho):
+    Nx, Ny, steps = 24, 3, 40
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y | orc.SINGLE_PHASE,
+                           period=0.0, lam=0.2, Cv=1.3)
+    s = orc.Sim(p, rho_uniform=rho)
+    x, _ = _grid(Nx, Ny)
+    k = 2 * np.pi * mode / Nx
+    eps = 1e-3 * p.T0
+    s.set_T(p.T0 + eps * np.sin(k * x))
+    s.step(steps)
+    T = s.moments()[3]
+    z = p.lam / (rho * p.Cv) * 2 * (np.cos(k) - 1)
+    expect = p.T0 + eps * _rk4_factor(z) ** steps * np.sin(k * x)
+    np.testing.assert_allclose(T, expect, rtol=0, atol=1e-13 * p.T0)
+
+
+def test_rk4_advection_mode(orc):
+    """Uniform flow U along x (set as the textbook equilibrium) carries the
+    mode: z = -i U sin k + D 2 (cos k - 1)."""
+    Nx, Ny, steps, U, rho = 20, 3, 60, 0.05, 0.8
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y | orc.SINGLE_PHASE,
+                           period=0.0, lam=0.05, Cv=2.0)
+    s = orc.Sim(p, rho_uniform=rho)
+    eu = E @ np.array([U, 0.0])
+    feq = W_EQ * rho * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * U * U)
+    s.set_f(np.broadcast_to(feq[:, None, None], (9, Ny, Nx)).copy())
+    x, _ = _grid(Nx, Ny)
+    k = 2 * np.pi * 2 / Nx
+    eps = 1e-3 * p.T0
+    s.set_T(p.T0 + eps * np.sin(k * x))
+    s.step(steps)
+    _, ux, uy, T, _, _ = s.moments()
+    np.testing.assert_allclose(ux, U, rtol=1e-13)
+    z = -1j * U * np.sin(k) + p.lam / (rho * p.Cv) * 2 * (np.cos(k) - 1)
+    expect = p.T0 + np.real(-1j * eps * _rk4_factor(z) ** steps * np.exp(1j * k * x))
+    np.testing.assert_allclose(T, expect, rtol=0, atol=1e-13 * p.T0)
