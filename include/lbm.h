@@ -1,0 +1,184 @@
+/*
+ * lbm.h -- C-ABI of the MI355X pseudopotential MRT lattice Boltzmann step.
+ *
+ * Method: W. Zhao, B. Xu, Y. Zhang, arXiv:1803.01756, Section 2.  One call of
+ * lbm_step(sim, 1) advances a D2Q9 channel between two plates by one time
+ * step:
+ *   - macroscopic density and half-force velocity (Eq. 13),
+ *   - pseudopotential psi(rho, T) from the Peng-Robinson EOS (Eqs. 10-11),
+ *   - Shan-Chen fluid-fluid force (Eq. 9), wall adhesion (Eq. 14), gravity
+ *     (Eq. 15) and the oscillating drive rho*g_osc*sin(2 pi n / period) along
+ *     +x,
+ *   - density-interpolated viscous relaxation time (Eqs. 4-5),
+ *   - MRT collision in moment space with Li's source term (Eqs. 6-8),
+ *   - classical RK4 of the energy equation (Eqs. 16-18) with isotropic
+ *     nine-point finite differences,
+ *   - streaming (Eq. 12) with half-way bounce-back at the plates.
+ * The plates are the solid rows y = 0 and y = Ny-1; x is periodic.
+ *
+ * Conventions for every entry point:
+ *   - Status codes only; nothing throws or exits.  On failure an output
+ *     handle is set to NULL and lbm_last_error() describes the cause.
+ *   - Host arrays are caller-owned and indexed [y*Nx + x], y = 0..Ny-1.
+ *   - Device memory and streams are plain pointers (hipStream_t is passed as
+ *     void*).  A NULL stream means the library creates its own.
+ *   - lbm_step only enqueues work.  Device faults and a non-finite state
+ *     surface on the next synchronising call (lbm_moments, lbm_reduce,
+ *     lbm_synchronize) as LBM_EDEVICE / LBM_EUNSTABLE.
+ *   - A simulation must not be used from two threads at once.
+ */
+#ifndef PAPER_1803_01756_LBM_H
+#define PAPER_1803_01756_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_sim lbm_sim;   /* opaque, library-owned */
+typedef struct lbm_pool lbm_pool; /* opaque slot pool for batched / served runs */
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* invalid argument or parameter set                   */
+    LBM_ENOMEM = -2,    /* device memory (or pool capacity) exhausted           */
+    LBM_EDEVICE = -3,   /* HIP runtime error                                    */
+    LBM_EUNSTABLE = -4, /* non-finite density, velocity or temperature found    */
+    LBM_ESTATE = -5     /* call not valid in the current state                  */
+} lbm_status;
+
+/* storage precision of the populations and the temperature */
+enum {
+    LBM_FP32_DEV = 0,          /* FP32 deviations f_i - w_i rho_ref, T - T_0   */
+    LBM_FP64 = 1,              /* FP64 deviations                              */
+    LBM_FP32_DEV_MASSEXACT = 2 /* FP32 deviations, rest population kept as an
+                                  FP32 (hi, lo) pair so that the total mass is
+                                  conserved to FP64 rounding                   */
+};
+
+/* flags */
+enum {
+    LBM_FREEZE_T = 1u,     /* isothermal: skip the temperature update           */
+    LBM_SINGLE_PHASE = 2u, /* F_m = 0 and no theta term (ideal-gas flow checks) */
+    LBM_PERIODIC_Y = 4u    /* no plates: periodic in y as well                  */
+};
+
+/* Parameters, named as in the paper.  lbm_params_default() fills the paper's
+ * values and the readings taken for the unstated ones; lbm_params_resolve()
+ * fills the derived fields left at <= 0. */
+typedef struct {
+    int32_t Nx, Ny;         /* nodes, solid plate rows included                    */
+    double a, b, R, omega;  /* Eq. 11: 3/49, 2/21, 1; acentric factor 0.344        */
+    double T_c;             /* Eq. 11 critical temperature; <= 0: derived          */
+    double G;               /* Eqs. 9-10 interaction strength, default -1          */
+    double theta;           /* Eq. 8 thermodynamic-consistency factor, 0.104       */
+    double G_w, psi_w;      /* Eq. 14 adhesion strength and wall potential         */
+    double s_rho, s_e, s_zeta, s_j, s_q; /* Eq. 3 rates; s_e must equal s_zeta    */
+    double tau_g, tau_l;    /* Eq. 5 viscous relaxation times of gas and liquid   */
+    double rho_g, rho_l;    /* Eq. 5 phase densities; <= 0: Maxwell at T_0        */
+    double C_v, lambda;     /* Eq. 16 heat capacity and conductivity, 5 and 0.25  */
+    double T_0, T_w;        /* initial fluid and plate temperatures               */
+    double g_osc, period;   /* drive amplitude and period in steps (<= 0: off)    */
+    double g_x, g_y;        /* Eq. 15 gravity                                      */
+    double rho_v;           /* Eq. 15 reference vapour density; <= 0: Maxwell gas */
+    double rho_ref;         /* density of the stored deviations; <= 0: rho_v      */
+    int32_t precision;      /* LBM_FP32_DEV, LBM_FP64 or LBM_FP32_DEV_MASSEXACT   */
+    uint32_t flags;         /* LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y   */
+} lbm_params;
+
+/* Fill *p with the defaults: Nx = 128, Ny = 32, a = 3/49, b = 2/21, R = 1,
+ * omega = 0.344, T_c derived, G = -1, theta = 0.104, G_w = psi_w = 0,
+ * s_rho = s_j = 1, s_e = s_zeta = 0.8, s_q = 1.1, tau_g = tau_l = 1,
+ * C_v = 5, lambda = 0.25 (Sec. 3.2), T_0 = 0.86 T_c, T_w = 0.80 T_c,
+ * g_osc = 1e-6, period = 2000, no gravity, FP32_DEV, no flags.  T_0, T_w
+ * and the densities stay <= 0 ("derive") until lbm_params_resolve(). */
+void lbm_params_default(lbm_params* p);
+
+/* Derive the fields left at <= 0: T_c (critical point of Eq. 11 with
+ * phi = 1), T_0 = 0.86 T_c, T_w = 0.80 T_c, rho_g and rho_l (Maxwell
+ * coexistence at T_0), rho_v = rho_g, rho_ref = rho_v.  LBM_EINVAL if T_0 is
+ * not below T_c while a coexistence density is requested. */
+lbm_status lbm_params_resolve(lbm_params* p);
+
+/* Critical point (rho_c, T_c) of the Peng-Robinson EOS of Eq. 11 and the
+ * coexistence densities at temperature T (equal pressure and chemical
+ * potential).  Host FP64. */
+lbm_status lbm_eos_critical(double a, double b, double R, double* rho_c, double* T_c);
+lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_g, double* rho_l,
+                               double* p_sat);
+
+/* Device bytes a simulation with these parameters needs (two population
+ * buffers, two temperature buffers, moment scratch), for callers that
+ * provide the memory themselves.  0 if the parameters are invalid. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Create a simulation at time level 0.
+ *   p          parameters (resolved internally; the caller's copy is not changed)
+ *   rho0       host array Nx*Ny of initial densities (solid rows ignored), or
+ *              NULL for the uniform density rho_v.  Populations start at the
+ *              rest equilibrium f_i = w_i rho0, T = T_0 on fluid nodes.
+ *   workspace  device memory of at least lbm_workspace_bytes(p) bytes, owned by
+ *              the caller and valid until lbm_destroy; NULL: the library
+ *              allocates and frees its own.
+ *   ws_bytes   size of workspace (ignored when workspace is NULL)
+ *   stream     hipStream_t all work is ordered on, or NULL for a private stream
+ *   out        receives the handle
+ * LBM_EINVAL: Nx < 3, Ny < 4 (Ny < 3 with LBM_PERIODIC_Y), G = 0, a relaxation
+ * rate outside (0, 2), tau <= 1/2, s_e != s_zeta, b*rho >= 1 at the initial
+ * state, or a workspace that is too small.  LBM_ENOMEM, LBM_EDEVICE. */
+lbm_status lbm_create(const lbm_params* p, const double* rho0, void* workspace,
+                      size_t ws_bytes, void* stream, lbm_sim** out);
+
+/* Enqueue n >= 0 time steps (asynchronous). */
+lbm_status lbm_step(lbm_sim* sim, int64_t n);
+
+/* Synchronise and copy rho, u (the half-force velocity of Eq. 13) and T at
+ * the current time level into caller-owned host arrays of Nx*Ny doubles
+ * (any may be NULL).  Solid rows give rho = 0, u = 0, T = T_w. */
+lbm_status lbm_moments(lbm_sim* sim, double* rho, double* ux, double* uy, double* T);
+
+/* Synchronise and reduce in FP64 with a fixed summation order:
+ * out[0] = sum rho, out[1] = sum rho u_x, out[2] = sum rho u_y,
+ * out[3] = sum rho C_v T, out[4] = number of non-finite nodes.
+ * Returns LBM_EUNSTABLE when out[4] > 0. */
+lbm_status lbm_reduce(lbm_sim* sim, double out[5]);
+
+/* Wait for all enqueued work; LBM_EDEVICE on a device error. */
+lbm_status lbm_synchronize(lbm_sim* sim);
+
+/* Destroy; NULL is accepted.  Frees library-owned memory and stream. */
+lbm_status lbm_destroy(lbm_sim* sim);
+
+int64_t lbm_time(const lbm_sim* sim);
+
+/* Parameters after resolution (derived fields filled). */
+lbm_status lbm_get_params(const lbm_sim* sim, lbm_params* out);
+
+/* Message of the last failure on this thread (never NULL). */
+const char* lbm_last_error(void);
+
+/* Checkpoint: lbm_state_bytes() bytes hold the time level, the parameters
+ * and the device state; lbm_load() restores a state saved from a simulation
+ * with the same grid and precision.  Both synchronise. */
+size_t lbm_state_bytes(const lbm_sim* sim);
+lbm_status lbm_save(lbm_sim* sim, void* host, size_t bytes);
+lbm_status lbm_load(lbm_sim* sim, const void* host, size_t bytes);
+
+/* Launch shape of the fused step kernel: each wave owns a strip of 54
+ * columns and marches over seg_rows fluid rows.  seg_rows <= 0 picks the
+ * shape from the library's tuning table (see lbm_autotune). */
+lbm_status lbm_set_launch(lbm_sim* sim, int32_t seg_rows);
+lbm_status lbm_get_launch(const lbm_sim* sim, int32_t* seg_rows, int32_t* waves);
+
+/* Time candidate launch shapes on this simulation (the state is saved and
+ * restored around the trials) and keep the fastest.  best_ms receives the
+ * best time per step (may be NULL). */
+lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_trial, double* best_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,89 @@
+// Internal interface between the C-ABI runtime (lbm_runtime.cpp) and the
+// HIP kernels (lbm_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbmk {
+
+// Owned columns per wave-strip: 64 lanes minus a 5-column halo on each side
+// (psi needs rho one column out, u needs psi one further, and each of the four
+// RK4 stages widens the temperature stencil by one more column).
+constexpr int kLanes = 64;
+constexpr int kHalo = 5;
+constexpr int kOwned = kLanes - 2 * kHalo;
+
+// Uniform physical constants, resolved on the host in FP64.  The kernels
+// read them from the kernel-argument segment (scalar registers).
+struct Phys {
+    double rho_ref, T_ref, dT_wall;     // storage references; T_w - T_ref
+    double a, b, R, kappa, inv_Tc;      // Eq. 11
+    double inv_G, negG;                 // Eq. 10 (1/G) and Eq. 9 (-G)
+    double psi_wall_eff;                // psi_w G_w / G: solid-row potential
+    double Gw_psiw;                     // G_w psi_w (Eq. 14 on the wall rows)
+    double c_e, c_z;                    // 12 theta / (tau_e - 1/2), same for zeta
+    double s_rho, s_e, s_z, s_j, s_q;   // Eq. 3 rates
+    double tau_g, dtau, rho_g, inv_drho;// Eq. 5 (inv_drho = 0: constant tau)
+    double inv_Cv, lambda;              // Eq. 16
+    double drive;                       // g_osc sin(2 pi n / period) at this step
+    double g_x, g_y, rho_v;             // Eq. 15
+    double rkA, rkB1, rkB2;             // R, a k (1+k)/sqrt(Tc), a k^2 / Tc
+    uint32_t flags;                     // LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y
+    uint32_t pad_;
+};
+
+struct Grid {
+    int Nx, Ny;        // nodes incl. plate rows
+    int pitch;         // elements per stored row (multiple of 64)
+    int rows;          // stored (fluid) rows
+    int y_first;       // y of stored row 0 (1 with plates, 0 periodic)
+    int periodic_y;
+    int n_strips, n_segs, seg_rows, n_units, n_blocks_pad;
+    unsigned plane;    // rows * pitch
+};
+
+template <class S>
+struct Bufs {
+    const S* fin;
+    S* fout;
+    const float* f0lo_in;  // mass-exact low part of the rest population
+    float* f0lo_out;
+    const S* Tin;
+    S* Tout;
+};
+
+constexpr int kWavesPerBlock = 4;
+
+// One fused time step (pull-stream + bounce-back, psi, forces, u, MRT
+// collision, RK4 temperature) over all units of the grid.
+hipError_t launch_step_f32(const Grid& g, const Phys& k, const Bufs<float>& b, bool mass_exact,
+                           hipStream_t s);
+hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, hipStream_t s);
+
+// rho, u (half force) and T at the current time level into device arrays of
+// Nx*Ny doubles; scratch holds 3*Nx*Ny doubles.
+hipError_t launch_moments_f32(const Grid& g, const Phys& k, const float* f, const float* f0lo,
+                              const float* T, double* scratch, double* rho, double* ux,
+                              double* uy, double* Tout, hipStream_t s);
+hipError_t launch_moments_f64(const Grid& g, const Phys& k, const double* f, const double* T,
+                              double* scratch, double* rho, double* ux, double* uy,
+                              double* Tout, hipStream_t s);
+
+// Rest-equilibrium start from a device density field rho0 (Nx*Ny doubles).
+hipError_t launch_init_f32(const Grid& g, const Phys& k, const double* rho0, float* f,
+                           float* f0lo, float* T, hipStream_t s);
+hipError_t launch_init_f64(const Grid& g, const Phys& k, const double* rho0, double* f,
+                           double* T, hipStream_t s);
+
+// Deterministic FP64 reduction of the moment arrays: out[5] = {sum rho,
+// sum rho ux, sum rho uy, sum rho Cv T, non-finite count}.  partials holds
+// kReduceBlocks*5 doubles.
+constexpr int kReduceBlocks = 256;
+hipError_t launch_reduce(const double* rho, const double* ux, const double* uy,
+                         const double* T, int n, double Cv, double* partials, double* out,
+                         hipStream_t s);
+
+}  // namespace lbmk

@@ -1,0 +1,809 @@
+// HIP kernels (gfx950 / CDNA4) of the pseudopotential MRT lattice Boltzmann
+// step with the coupled RK4 temperature update, arXiv:1803.01756 Section 2.
+//
+// Fused step layout.  Populations are structure-of-arrays planes
+// [9][rows][pitch] of deviations d_i = f_i - w_i rho_ref (x fastest, pitch a
+// multiple of 64), temperature a plane [rows][pitch] of T - T_ref.  Only the
+// fluid rows are stored.  The buffers hold post-collision values, so a step
+// pulls f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) where x - e_i is a plate
+// (half-way bounce-back), and writes f*(x) in place of its own node into the
+// other buffer of the A-B pair.
+//
+// Each wave owns a strip of 54 columns (lane l holds column strip*54 - 5 + l,
+// periodic in x) and marches upward over a segment of fluid rows.  Neighbour
+// columns come from the adjacent lanes through DPP wave shifts, neighbour rows
+// from registers, so the whole step is one pass without LDS or barriers.  In
+// the iteration whose leading row is k the wave
+//   A  pulls row k and computes rho, j, psi(rho, T) there,
+//   B  computes the forces, u and the MRT collision on row k-1,
+//   C..F evaluate the RK4 stages h1..h4 on rows k-2 .. k-5,
+// so every stage only needs rows that earlier stages of the same or previous
+// iterations produced.  A stage loses one valid lane per side, hence the
+// 5-column halo; rows of the halo above and below the segment are recomputed
+// (5 extra leading and trailing iterations).
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbmk {
+namespace {
+
+constexpr uint32_t kFreezeT = 1u, kSinglePhase = 2u;
+
+// ---- lane shifts (DPP wave_shr:1 / wave_shl:1) ---------------------------
+// at_xm(v): the value lane l-1 holds (column x-1); at_xp: lane l+1 (x+1).  The
+// edge lanes keep their own value; they lie in the halo.
+__device__ __forceinline__ int dpp_shr1(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_shl1(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float at_xm(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
+__device__ __forceinline__ float at_xp(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
+__device__ __forceinline__ double at_xm(double v) {
+    int2 w = *reinterpret_cast<int2*>(&v);
+    w.x = dpp_shr1(w.x);
+    w.y = dpp_shr1(w.y);
+    return *reinterpret_cast<double*>(&w);
+}
+__device__ __forceinline__ double at_xp(double v) {
+    int2 w = *reinterpret_cast<int2*>(&v);
+    w.x = dpp_shl1(w.x);
+    w.y = dpp_shl1(w.y);
+    return *reinterpret_cast<double*>(&w);
+}
+
+template <class R>
+struct Tri {  // a row value at x, x-1 and x+1
+    R c, m, p;
+};
+template <class R>
+__device__ __forceinline__ Tri<R> tri(R v) {
+    Tri<R> t;
+    t.c = v;
+    t.m = at_xm(v);
+    t.p = at_xp(v);
+    return t;
+}
+template <class R>
+__device__ __forceinline__ Tri<R> tri_const(R v) {
+    Tri<R> t;
+    t.c = v;
+    t.m = v;
+    t.p = v;
+    return t;
+}
+
+// ---- rows -----------------------------------------------------------------
+struct RowK {
+    bool fluid;   // stored fluid row
+    bool bb_lo;   // the row below is a plate (bounce-back of e_y = +1 links)
+    bool bb_hi;   // the row above is a plate
+    int sr;       // stored row index
+};
+__device__ __forceinline__ RowK row_info(int y, const Grid& g) {
+    RowK r;
+    if (g.periodic_y) {
+        int yy = y % g.Ny;
+        if (yy < 0) yy += g.Ny;
+        r.fluid = true;
+        r.bb_lo = r.bb_hi = false;
+        r.sr = yy;
+        return r;
+    }
+    r.fluid = (y >= 1 && y <= g.Ny - 2);
+    r.bb_lo = (y == 1);
+    r.bb_hi = (y == g.Ny - 2);
+    r.sr = y - 1;
+    return r;
+}
+
+// Pull of Eq. 12 for one stored row: f_i(x) = f*_i(x - e_i) or, across a
+// plate, f*_opp(i)(x).  Velocity order of Eq. 2: 0 rest, 1 +x, 2 +y, 3 -x,
+// 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-).
+template <class S>
+__device__ __forceinline__ void pull_row(const S* __restrict__ f, const Grid& g, const RowK& r,
+                                         unsigned x, unsigned xm, unsigned xp, S d[9]) {
+    const unsigned P = g.plane, pitch = (unsigned)g.pitch;
+    const unsigned rc = (unsigned)r.sr * pitch;
+    unsigned rdn, rup;
+    if (g.periodic_y) {
+        int a = r.sr - 1, b = r.sr + 1;
+        if (a < 0) a += g.rows;
+        if (b >= g.rows) b -= g.rows;
+        rdn = (unsigned)a * pitch;
+        rup = (unsigned)b * pitch;
+    } else {
+        rdn = rc - pitch;
+        rup = rc + pitch;
+    }
+    const unsigned o0 = rc + x;
+    const unsigned o1 = P + rc + xm;
+    const unsigned o3 = 3 * P + rc + xp;
+    const unsigned o2 = r.bb_lo ? 4 * P + rc + x : 2 * P + rdn + x;
+    const unsigned o5 = r.bb_lo ? 7 * P + rc + x : 5 * P + rdn + xm;
+    const unsigned o6 = r.bb_lo ? 8 * P + rc + x : 6 * P + rdn + xp;
+    const unsigned o4 = r.bb_hi ? 2 * P + rc + x : 4 * P + rup + x;
+    const unsigned o7 = r.bb_hi ? 5 * P + rc + x : 7 * P + rup + xp;
+    const unsigned o8 = r.bb_hi ? 6 * P + rc + x : 8 * P + rup + xm;
+    d[0] = f[o0];
+    d[1] = f[o1];
+    d[2] = f[o2];
+    d[3] = f[o3];
+    d[4] = f[o4];
+    d[5] = f[o5];
+    d[6] = f[o6];
+    d[7] = f[o7];
+    d[8] = f[o8];
+}
+
+// Eqs. 10-11: psi = sqrt(2 (P_EOS(rho, T) - rho/3) / G), clamped at 0.
+// FP64 throughout: the Shan-Chen force is a difference of neighbouring psi
+// values and the FP32 rounding of psi itself would be of the order of that
+// difference in a nearly uniform vapour.
+template <bool kSqrtPhiF32>
+__device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k) {
+    double st;
+    if (kSqrtPhiF32)
+        st = (double)__builtin_sqrtf((float)(T * k.inv_Tc));
+    else
+        st = sqrt(T * k.inv_Tc);
+    const double s = 1.0 + k.kappa * (1.0 - st);
+    const double br = k.b * rho;
+    const double P = rho * k.R * T / (1.0 - br) - k.a * (s * s) * rho * rho / (1.0 + br * (2.0 - br));
+    const double arg = 2.0 * (P - rho * (1.0 / 3.0)) * k.inv_G;
+    return arg > 0.0 ? sqrt(arg) : 0.0;
+}
+
+// Eq. 9 + Eq. 14 in one sum: the solid rows carry the effective potential
+// psi_w G_w / G, so -G psi(x) sum_i w_i phi(x + e_i) e_i is F_m + F_ads.
+__device__ __forceinline__ void pair_force(const Tri<double>& pS, const Tri<double>& pC,
+                                           const Tri<double>& pN, double negG, double& Fx,
+                                           double& Fy) {
+    const double sx = (pC.p - pC.m) * (1.0 / 3.0) + ((pN.p - pN.m) + (pS.p - pS.m)) * (1.0 / 12.0);
+    const double sy = (pN.c - pS.c) * (1.0 / 3.0) + ((pN.p + pN.m) - (pS.p + pS.m)) * (1.0 / 12.0);
+    Fx = negG * pC.c * sx;
+    Fy = negG * pC.c * sy;
+}
+
+// Eq. 14 alone on the first / last fluid row: the three links crossing a
+// plate carry weight 1/3 + 2/12 = 1/2.
+__device__ __forceinline__ double wall_adhesion_y(const RowK& r, double psi_c, const Phys& k) {
+    double f = 0.0;
+    if (r.bb_lo) f += 0.5 * k.Gw_psiw * psi_c;
+    if (r.bb_hi) f -= 0.5 * k.Gw_psiw * psi_c;
+    return f;
+}
+
+// MRT collision, Eqs. 6-8, in deviation moments: m'_k = m_k - rho_ref (M w)_k.
+// Returns the post-collision deviations in d (overwritten).
+template <class R>
+__device__ __forceinline__ void collide(R d[9], R drho, R rho, R ux, R uy, R Fx, R Fy, R th,
+                                        R sv, const Phys& k) {
+    const R s_rho = (R)k.s_rho, s_e = (R)k.s_e, s_z = (R)k.s_z, s_j = (R)k.s_j, s_q = (R)k.s_q;
+    const R axis = (d[1] + d[2]) + (d[3] + d[4]);
+    const R diag = (d[5] + d[6]) + (d[7] + d[8]);
+    R m[9];
+    m[0] = drho;
+    m[1] = (R)-4 * d[0] - axis + (R)2 * diag;
+    m[2] = (R)4 * d[0] - (R)2 * axis + diag;
+    m[3] = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    m[4] = (R)2 * (d[3] - d[1]) + (d[5] - d[6]) + (d[8] - d[7]);
+    m[5] = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    m[6] = (R)2 * (d[4] - d[2]) + (d[5] + d[6]) - (d[7] + d[8]);
+    m[7] = (d[1] + d[3]) - (d[2] + d[4]);
+    m[8] = (d[5] + d[7]) - (d[6] + d[8]);
+    const R jx = rho * ux, jy = rho * uy;
+    const R rinv = (R)1 / rho;
+    const R j2r = (jx * jx + jy * jy) * rinv;
+    R meq[9];
+    meq[0] = drho;
+    meq[1] = (R)-2 * drho + (R)3 * j2r;
+    meq[2] = drho - (R)3 * j2r;
+    meq[3] = jx;
+    meq[4] = -jx;
+    meq[5] = jy;
+    meq[6] = -jy;
+    meq[7] = (jx * jx - jy * jy) * rinv;
+    meq[8] = jx * jy * rinv;
+    const R uF = ux * Fx + uy * Fy;
+    R S[9];
+    S[0] = (R)0;
+    S[1] = (R)6 * uF + (R)k.c_e * th;
+    S[2] = (R)-6 * uF - (R)k.c_z * th;
+    S[3] = Fx;
+    S[4] = -Fx;
+    S[5] = Fy;
+    S[6] = -Fy;
+    S[7] = (R)2 * (ux * Fx - uy * Fy);
+    S[8] = ux * Fy + uy * Fx;
+    const R s[9] = {s_rho, s_e, s_z, s_j, s_q, s_j, s_q, sv, sv};
+    R a[9];
+    const R nrm[9] = {(R)1 / 9, (R)1 / 36, (R)1 / 36, (R)1 / 6, (R)1 / 12,
+                      (R)1 / 6, (R)1 / 12, (R)1 / 4, (R)1 / 4};
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        a[q] = (m[q] - s[q] * (m[q] - meq[q]) + ((R)1 - (R)0.5 * s[q]) * S[q]) * nrm[q];
+    // f* = M^T diag(1/|M_k|^2) m*
+    const R b0 = a[0] - a[1] - (R)2 * a[2];
+    const R c0 = a[0] + (R)2 * a[1] + a[2];
+    d[0] = a[0] - (R)4 * a[1] + (R)4 * a[2];
+    d[1] = b0 + a[3] - (R)2 * a[4] + a[7];
+    d[2] = b0 + a[5] - (R)2 * a[6] - a[7];
+    d[3] = b0 - a[3] + (R)2 * a[4] + a[7];
+    d[4] = b0 - a[5] + (R)2 * a[6] - a[7];
+    d[5] = c0 + a[3] + a[4] + a[5] + a[6] + a[8];
+    d[6] = c0 - a[3] - a[4] + a[5] + a[6] - a[8];
+    d[7] = c0 - a[3] - a[4] - a[5] - a[6] + a[8];
+    d[8] = c0 + a[3] + a[4] - a[5] - a[6] - a[8];
+}
+
+// Per-row coefficients of K(T) (Eq. 16) with rho(n), u(n) frozen:
+//   K = -(u . grad T) + q3 lap T - q1 T - q2 sqrt(T),
+// using T (dP/dT)_rho = (A - B2) T + B1 sqrt(T), A = rho R / (1 - b rho),
+// B1 = a k (1 + k) rho^2 / (sqrt(Tc) D), B2 = a k^2 rho^2 / (Tc D),
+// D = 1 + 2 b rho - b^2 rho^2, and c = 1 / (rho C_v):
+//   q1 = c div(u) (A - B2), q2 = c div(u) B1, q3 = c lambda.
+template <class R>
+struct Coef {
+    R ux, uy, q1, q2, q3;
+};
+template <class R>
+__device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, const Phys& k) {
+    const R br = (R)k.b * rho;
+    const R Dinv = (R)1 / ((R)1 + br * ((R)2 - br));
+    const R A = rho * (R)k.rkA / ((R)1 - br);
+    const R r2D = rho * rho * Dinv;
+    const R c = (R)k.inv_Cv / rho;
+    Coef<R> q;
+    q.ux = ux;
+    q.uy = uy;
+    q.q1 = c * divu * (A - (R)k.rkB2 * r2D);
+    q.q2 = c * divu * (R)k.rkB1 * r2D;
+    q.q3 = c * (R)k.lambda;
+    return q;
+}
+template <class R>
+__device__ __forceinline__ R sqrt_r(R v);
+template <>
+__device__ __forceinline__ float sqrt_r<float>(float v) { return __builtin_sqrtf(v); }
+template <>
+__device__ __forceinline__ double sqrt_r<double>(double v) { return sqrt(v); }
+
+// K(T) on the stage field (deviations tS, tC, tN of rows y-1, y, y+1).
+template <class R>
+__device__ __forceinline__ R heat_rhs(const Tri<R>& tS, const Tri<R>& tC, const Tri<R>& tN,
+                                      const Coef<R>& q, R T_ref) {
+    const R third = (R)1 / 3, twelfth = (R)1 / 12;
+    const R tx = (tC.p - tC.m) * third + ((tN.p + tS.p) - (tN.m + tS.m)) * twelfth;
+    const R ty = (tN.c - tS.c) * third + ((tN.p + tN.m) - (tS.p + tS.m)) * twelfth;
+    const R ax = (tC.p + tC.m) + (tN.c + tS.c);
+    const R dg = (tN.p + tN.m) + (tS.p + tS.m);
+    const R lap = ax * ((R)2 / 3) + dg * ((R)1 / 6) - tC.c * ((R)10 / 3);
+    const R Tabs = T_ref + tC.c;
+    return -(q.ux * tx + q.uy * ty) + q.q3 * lap - q.q1 * Tabs - q.q2 * sqrt_r(Tabs);
+}
+
+// divergence of u at row y from rows y-1 (uS), y (uC), y+1 (uN)
+template <class R>
+__device__ __forceinline__ R div_u(const Tri<R>& xS, const Tri<R>& xC, const Tri<R>& xN,
+                                   const Tri<R>& yS, const Tri<R>& yC, const Tri<R>& yN) {
+    const R third = (R)1 / 3, twelfth = (R)1 / 12;
+    return ((xC.p - xC.m) + (yN.c - yS.c)) * third +
+           (((xN.p - xN.m) + (xS.p - xS.m)) + ((yN.p + yN.m) - (yS.p + yS.m))) * twelfth;
+}
+
+template <class S>
+struct RealOf;
+template <>
+struct RealOf<float> {
+    using T = float;
+};
+template <>
+struct RealOf<double> {
+    using T = double;
+};
+
+// XCD-aware unit index: blocks are dispatched round-robin over the eight
+// XCDs, so consecutive units (neighbouring strips, which share halo columns)
+// are mapped to blocks that land on the same XCD and its L2.
+__device__ __forceinline__ int unit_of_block(int nblocks_pad) {
+    const int b = blockIdx.x;
+    const int per = nblocks_pad >> 3;
+    return ((b & 7) * per + (b >> 3));
+}
+
+template <class S, bool kMX>
+__global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Phys k, Bufs<S> B) {
+    using R = typename RealOf<S>::T;
+    constexpr bool kF32 = sizeof(S) == 4;
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (unit >= g.n_units) return;  // whole waves only
+    const int strip = unit % g.n_strips;
+    const int seg = unit / g.n_strips;
+
+    // lane column and its periodic neighbours
+    int cx = strip * kOwned - kHalo + lane;
+    cx %= g.Nx;
+    if (cx < 0) cx += g.Nx;
+    const unsigned x = (unsigned)cx;
+    const unsigned xm = (unsigned)(cx == 0 ? g.Nx - 1 : cx - 1);
+    const unsigned xp = (unsigned)(cx == g.Nx - 1 ? 0 : cx + 1);
+    const int own_w = min(kOwned, g.Nx - strip * kOwned);
+    const bool own_lane = lane >= kHalo && lane < kHalo + own_w;
+
+    const int ya = g.y_first + seg * g.seg_rows;
+    const int yb = min(ya + g.seg_rows, g.y_first + g.rows);
+
+    const bool freezeT = (k.flags & kFreezeT) != 0;
+    const bool single = (k.flags & kSinglePhase) != 0;
+    const R T_ref = (R)k.T_ref;
+    const R dTw = (R)k.dT_wall;
+    const R rho_ref = (R)k.rho_ref;
+
+    // ---- register row windows ----
+    // pulled deviations and derived values of rows k (cur) and k-1 (prv)
+    R dPrv[9], dCur[9];
+    R rhoCur = 0, rhoPrv = 0, rhoP2 = 0;  // rho of rows k, k-1, k-2
+    R drCur = 0, drPrv = 0;
+    R jxCur = 0, jyCur = 0, jxPrv = 0, jyPrv = 0;
+    Tri<double> psi0, psi1, psi2;  // rows k, k-1, k-2
+    // T(n) deviations: rows k .. k-5 (centre), shifted copies for rows k .. k-3
+    Tri<R> tn0, tn1, tn2, tn3;
+    R tn4 = 0, tn5 = 0;
+    // velocity rows k-1, k-2, k-3
+    Tri<R> ux1, ux2, ux3, uy1, uy2, uy3;
+    // heat coefficients rows k-2 .. k-5
+    Coef<R> cf2, cf3, cf4, cf5;
+    // RK stage fields: T1 rows k-2..k-4, T2 rows k-3..k-5, T3 rows k-4..k-6
+    Tri<R> t1a, t1b, t1c, t2a, t2b, t2c, t3a, t3b, t3c;
+    R acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0;  // accumulated h's, rows k-2..k-5
+    double drdCur = 0.0, drdPrv = 0.0;         // mass-exact: FP64 deviation density
+
+#pragma unroll
+    for (int q = 0; q < 9; ++q) dPrv[q] = dCur[q] = 0;
+    psi0 = psi1 = psi2 = tri_const<double>(0.0);
+    tn0 = tn1 = tn2 = tn3 = tri_const<R>(dTw);
+    ux1 = ux2 = ux3 = uy1 = uy2 = uy3 = tri_const<R>(0);
+    cf2 = cf3 = cf4 = cf5 = Coef<R>{0, 0, 0, 0, 0};
+    t1a = t1b = t1c = t2a = t2b = t2c = t3a = t3b = t3c = tri_const<R>(dTw);
+
+    const S* __restrict__ fin = B.fin;
+    const S* __restrict__ Tin = B.Tin;
+
+    for (int kr = ya - kHalo; kr < yb + kHalo; ++kr) {
+        // ------------- stage A: pull row kr, rho, j, psi ------------------
+        const RowK rA = row_info(kr, g);
+        Tri<double> psiA;
+        R dTA;
+        if (rA.fluid) {
+            S raw[9];
+            pull_row<S>(fin, g, rA, x, xm, xp, raw);
+            const S rawT = Tin[(unsigned)rA.sr * (unsigned)g.pitch + x];
+            R lo = 0;
+            if (kMX) lo = (R)B.f0lo_in[(unsigned)rA.sr * (unsigned)g.pitch + x];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) dCur[q] = (R)raw[q];
+            double drd;
+            if (kMX) {
+                drd = (double)dCur[0] + (double)lo;
+#pragma unroll
+                for (int q = 1; q < 9; ++q) drd += (double)dCur[q];
+            } else {
+                R s = ((dCur[0] + dCur[1]) + (dCur[2] + dCur[3])) +
+                      ((dCur[4] + dCur[5]) + (dCur[6] + dCur[7])) + dCur[8];
+                drd = (double)s;
+            }
+            drCur = (R)drd;
+            drdCur = drd;
+            jxCur = (dCur[1] - dCur[3]) + (dCur[5] - dCur[6]) + (dCur[8] - dCur[7]);
+            jyCur = (dCur[2] - dCur[4]) + (dCur[5] + dCur[6]) - (dCur[7] + dCur[8]);
+            const double rho_d = k.rho_ref + drd;
+            rhoCur = (R)rho_d;
+            dTA = (R)rawT;
+            const double Td = k.T_ref + (double)dTA;
+            psiA = tri<double>(psi_eos<kF32>(rho_d, Td, k));
+        } else {
+            drCur = 0;
+            drdCur = 0.0;
+            rhoCur = rho_ref;
+            jxCur = jyCur = 0;
+            dTA = dTw;
+            psiA = tri_const<double>(k.psi_wall_eff);
+        }
+        psi0 = psiA;
+        tn0 = tri<R>(dTA);
+
+        // ------------- stage B: forces, u, collision on row kr-1 ---------
+        const RowK rB = row_info(kr - 1, g);
+        Tri<R> uxB, uyB;
+        if (rB.fluid) {
+            double Fxd = 0.0, Fyd = 0.0, Fmx = 0.0, Fmy = 0.0;
+            if (!single) {
+                pair_force(psi2, psi1, psi0, k.negG, Fxd, Fyd);
+                Fmx = Fxd;
+                Fmy = Fyd - wall_adhesion_y(rB, psi1.c, k);
+            } else {
+                Fyd = wall_adhesion_y(rB, psi1.c, k);
+            }
+            const R rho = rhoPrv;
+            R Fx = (R)Fxd + rho * (R)k.drive + (rho - (R)k.rho_v) * (R)k.g_x;
+            R Fy = (R)Fyd + (rho - (R)k.rho_v) * (R)k.g_y;
+            const R rinv = (R)1 / rho;
+            const R ux = (jxPrv + (R)0.5 * Fx) * rinv;
+            const R uy = (jyPrv + (R)0.5 * Fy) * rinv;
+            uxB = tri<R>(ux);
+            uyB = tri<R>(uy);
+            if (kr - 1 >= ya && kr - 1 < yb) {
+                // Eq. 8 theta term uses |F_m|^2 / psi^2 of the fluid-fluid force
+                R th = 0;
+                if (!single && psi1.c > 0.0) th = (R)((Fmx * Fmx + Fmy * Fmy) / (psi1.c * psi1.c));
+                // Eq. 5 with a clamped fraction
+                R fr = (rho - (R)k.rho_g) * (R)k.inv_drho;
+                fr = fr < (R)0 ? (R)0 : (fr > (R)1 ? (R)1 : fr);
+                const R sv = (R)1 / ((R)k.tau_g + fr * (R)k.dtau);
+                R dn[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) dn[q] = dPrv[q];
+                collide<R>(dn, drPrv, rho, ux, uy, Fx, Fy, th, sv, k);
+                if (own_lane) {
+                    const unsigned o = (unsigned)rB.sr * (unsigned)g.pitch + x;
+                    S* __restrict__ fo = B.fout;
+                    if (kMX) {
+                        // rest population takes whatever keeps sum_i d_i equal to
+                        // the pre-collision deviation density (FP64), as (hi, lo)
+                        double rest = drdPrv;
+#pragma unroll
+                        for (int q = 1; q < 9; ++q) rest -= (double)(S)dn[q];
+                        const float hi = (float)rest;
+                        fo[o] = (S)hi;
+                        B.f0lo_out[o] = (float)(rest - (double)hi);
+                    } else {
+                        fo[o] = (S)dn[0];
+                    }
+#pragma unroll
+                    for (int q = 1; q < 9; ++q) fo[q * g.plane + o] = (S)dn[q];
+                }
+            }
+        } else {
+            uxB = tri_const<R>(0);
+            uyB = tri_const<R>(0);
+        }
+        ux1 = uxB;
+        uy1 = uyB;
+
+        if (!freezeT) {
+            // ------------- stage C: div u, coefficients, h1 on row kr-2 ---
+            const RowK rC = row_info(kr - 2, g);
+            Tri<R> t1;
+            if (rC.fluid) {
+                const R dv = div_u<R>(ux3, ux2, ux1, uy3, uy2, uy1);
+                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, k);
+                const R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
+                acc2 = h1;
+                t1 = tri<R>(tn2.c + (R)0.5 * h1);
+            } else {
+                t1 = tri_const<R>(dTw);
+                acc2 = 0;
+            }
+            t1a = t1;
+            // ------------- stage D: h2 on row kr-3 ------------------------
+            const RowK rD = row_info(kr - 3, g);
+            Tri<R> t2;
+            if (rD.fluid) {
+                const R h2 = heat_rhs<R>(t1c, t1b, t1a, cf3, T_ref);
+                acc3 += (R)2 * h2;
+                t2 = tri<R>(tn3.c + (R)0.5 * h2);
+            } else {
+                t2 = tri_const<R>(dTw);
+            }
+            t2a = t2;
+            // ------------- stage E: h3 on row kr-4 ------------------------
+            const RowK rE = row_info(kr - 4, g);
+            Tri<R> t3;
+            if (rE.fluid) {
+                const R h3 = heat_rhs<R>(t2c, t2b, t2a, cf4, T_ref);
+                acc4 += (R)2 * h3;
+                t3 = tri<R>(tn4 + h3);
+            } else {
+                t3 = tri_const<R>(dTw);
+            }
+            t3a = t3;
+            // ------------- stage F: h4 and T(n+1) on row kr-5 -------------
+            const RowK rF = row_info(kr - 5, g);
+            if (rF.fluid && kr - 5 >= ya && kr - 5 < yb) {
+                const R h4 = heat_rhs<R>(t3c, t3b, t3a, cf5, T_ref);
+                const R tnew = tn5 + (acc5 + h4) * ((R)1 / 6);
+                if (own_lane) B.Tout[(unsigned)rF.sr * (unsigned)g.pitch + x] = (S)tnew;
+            }
+        }
+
+        // ------------- shift the windows one row ---------------------------
+        tn5 = tn4;
+        tn4 = tn3.c;
+        tn3 = tn2;
+        tn2 = tn1;
+        tn1 = tn0;
+        psi2 = psi1;
+        psi1 = psi0;
+        ux3 = ux2;
+        ux2 = ux1;
+        uy3 = uy2;
+        uy2 = uy1;
+        cf5 = cf4;
+        cf4 = cf3;
+        cf3 = cf2;
+        acc5 = acc4;
+        acc4 = acc3;
+        acc3 = acc2;
+        t1c = t1b;
+        t1b = t1a;
+        t2c = t2b;
+        t2b = t2a;
+        t3c = t3b;
+        t3b = t3a;
+        rhoP2 = rhoPrv;
+        rhoPrv = rhoCur;
+        drPrv = drCur;
+        jxPrv = jxCur;
+        jyPrv = jyCur;
+        drdPrv = drdCur;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dPrv[q] = dCur[q];
+    }
+}
+
+// ---- moments: two passes over all nodes ------------------------------------
+// pass 1: rho, psi, j (and T) per node into scratch; pass 2: forces and u.
+template <class S, bool kMX>
+__global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __restrict__ f,
+                                                     const float* __restrict__ f0lo,
+                                                     const S* __restrict__ T,
+                                                     double* __restrict__ scratch,
+                                                     double* __restrict__ rho_out,
+                                                     double* __restrict__ T_out) {
+    constexpr bool kF32 = sizeof(S) == 4;
+    const int n = g.Nx * g.Ny;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int y = i / g.Nx, cx = i - y * g.Nx;
+    double* psi = scratch;
+    double* jx = scratch + n;
+    double* jy = scratch + 2 * n;
+    const RowK r = row_info(y, g);
+    if (!r.fluid) {
+        psi[i] = k.psi_wall_eff;
+        jx[i] = jy[i] = 0.0;
+        rho_out[i] = 0.0;
+        T_out[i] = k.T_ref + k.dT_wall;
+        return;
+    }
+    const unsigned x = (unsigned)cx;
+    const unsigned xm = (unsigned)(cx == 0 ? g.Nx - 1 : cx - 1);
+    const unsigned xp = (unsigned)(cx == g.Nx - 1 ? 0 : cx + 1);
+    S d[9];
+    pull_row<S>(f, g, r, x, xm, xp, d);
+    double dr = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) dr += (double)d[q];
+    if (kMX) dr += (double)f0lo[(unsigned)r.sr * (unsigned)g.pitch + x];
+    const double rho = k.rho_ref + dr;
+    const double Td = k.T_ref + (double)T[(unsigned)r.sr * (unsigned)g.pitch + x];
+    rho_out[i] = rho;
+    T_out[i] = Td;
+    psi[i] = psi_eos<kF32>(rho, Td, k);
+    jx[i] = ((double)d[1] - (double)d[3]) + ((double)d[5] - (double)d[6]) +
+            ((double)d[8] - (double)d[7]);
+    jy[i] = ((double)d[2] - (double)d[4]) + ((double)d[5] + (double)d[6]) -
+            ((double)d[7] + (double)d[8]);
+}
+
+__global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
+                                                     const double* __restrict__ scratch,
+                                                     const double* __restrict__ rho_in,
+                                                     double* __restrict__ ux_out,
+                                                     double* __restrict__ uy_out) {
+    const int n = g.Nx * g.Ny;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int y = i / g.Nx, cx = i - y * g.Nx;
+    const RowK r = row_info(y, g);
+    if (!r.fluid) {
+        ux_out[i] = uy_out[i] = 0.0;
+        return;
+    }
+    const double* psi = scratch;
+    const double* jx = scratch + n;
+    const double* jy = scratch + 2 * n;
+    const int xm = cx == 0 ? g.Nx - 1 : cx - 1;
+    const int xp = cx == g.Nx - 1 ? 0 : cx + 1;
+    int ys = y - 1, yn = y + 1;
+    if (g.periodic_y) {
+        if (ys < 0) ys += g.Ny;
+        if (yn >= g.Ny) yn -= g.Ny;
+    }
+    Tri<double> pS, pC, pN;
+    pS.c = psi[ys * g.Nx + cx];
+    pS.m = psi[ys * g.Nx + xm];
+    pS.p = psi[ys * g.Nx + xp];
+    pC.c = psi[y * g.Nx + cx];
+    pC.m = psi[y * g.Nx + xm];
+    pC.p = psi[y * g.Nx + xp];
+    pN.c = psi[yn * g.Nx + cx];
+    pN.m = psi[yn * g.Nx + xm];
+    pN.p = psi[yn * g.Nx + xp];
+    double Fx = 0.0, Fy = 0.0;
+    if (!(k.flags & kSinglePhase))
+        pair_force(pS, pC, pN, k.negG, Fx, Fy);
+    else
+        Fy = wall_adhesion_y(r, pC.c, k);
+    const double rho = rho_in[i];
+    Fx += rho * k.drive + (rho - k.rho_v) * k.g_x;
+    Fy += (rho - k.rho_v) * k.g_y;
+    ux_out[i] = (jx[i] + 0.5 * Fx) / rho;
+    uy_out[i] = (jy[i] + 0.5 * Fy) / rho;
+}
+
+// ---- initial state ----------------------------------------------------------
+// Buffers hold post-collision values, so the start state is the field that
+// the first pull turns into f_i(x, 0) = w_i rho0(x): d*_i(z) = w_i (rho0(z + e_i)
+// - rho_ref), or w_i (rho0(z) - rho_ref) where z + e_i is a plate.
+template <class S, bool kMX>
+__global__ __launch_bounds__(256) void init_kernel(Grid g, Phys k, const double* __restrict__ rho0,
+                                                   S* __restrict__ f, float* __restrict__ f0lo,
+                                                   S* __restrict__ T) {
+    const int n = g.rows * g.Nx;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int sr = i / g.Nx, cx = i - sr * g.Nx;
+    const int y = sr + g.y_first;
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const unsigned o = (unsigned)sr * (unsigned)g.pitch + (unsigned)cx;
+    for (int q = 0; q < 9; ++q) {
+        int tx = cx + ex[q];
+        tx = tx < 0 ? tx + g.Nx : (tx >= g.Nx ? tx - g.Nx : tx);
+        int ty = y + ey[q];
+        bool solid = false;
+        if (g.periodic_y) {
+            ty = ty < 0 ? ty + g.Ny : (ty >= g.Ny ? ty - g.Ny : ty);
+        } else {
+            solid = (ty == 0 || ty == g.Ny - 1);
+        }
+        const double r = solid ? rho0[y * g.Nx + cx] : rho0[ty * g.Nx + tx];
+        const double v = w[q] * (r - k.rho_ref);
+        if (kMX && q == 0) {
+            const float hi = (float)v;
+            f[o] = (S)hi;
+            f0lo[o] = (float)(v - (double)hi);
+        } else {
+            f[q * g.plane + o] = (S)v;
+        }
+    }
+    T[o] = (S)0;  // T = T_0 = T_ref
+}
+
+// ---- deterministic FP64 reduction ------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void reduce_pass1(const double* __restrict__ rho,
+                                                    const double* __restrict__ ux,
+                                                    const double* __restrict__ uy,
+                                                    const double* __restrict__ T, int n,
+                                                    double Cv, double* __restrict__ partials) {
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double r = rho[i], a = ux[i], b = uy[i], t = T[i];
+        if (!(isfinite(r) && isfinite(a) && isfinite(b) && isfinite(t))) {
+            s[4] += 1.0;
+            continue;
+        }
+        s[0] += r;
+        s[1] += r * a;
+        s[2] += r * b;
+        s[3] += r * Cv * t;
+    }
+    __shared__ double red[4][5];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const double t = wave_sum(s[q]);
+        if (ln == 0) red[wv][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int q = threadIdx.x;
+        partials[blockIdx.x * 5 + q] = ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q]));
+    }
+}
+
+__global__ __launch_bounds__(64) void reduce_pass2(const double* __restrict__ partials, int nb,
+                                                   double* __restrict__ out) {
+    if (threadIdx.x < 5) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += partials[b * 5 + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+inline int blocks_for(int n, int bs) { return (n + bs - 1) / bs; }
+
+}  // namespace
+
+template <class S, bool kMX>
+static hipError_t step_impl(const Grid& g, const Phys& k, const Bufs<S>& b, hipStream_t s) {
+    if (g.n_units <= 0) return hipSuccess;
+    hipLaunchKernelGGL((step_kernel<S, kMX>), dim3(g.n_blocks_pad), dim3(kLanes * kWavesPerBlock),
+                       0, s, g, k, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_f32(const Grid& g, const Phys& k, const Bufs<float>& b, bool mass_exact,
+                           hipStream_t s) {
+    return mass_exact ? step_impl<float, true>(g, k, b, s) : step_impl<float, false>(g, k, b, s);
+}
+hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, hipStream_t s) {
+    return step_impl<double, false>(g, k, b, s);
+}
+
+template <class S, bool kMX>
+static hipError_t moments_impl(const Grid& g, const Phys& k, const S* f, const float* f0lo,
+                               const S* T, double* scratch, double* rho, double* ux, double* uy,
+                               double* Tout, hipStream_t s) {
+    const int n = g.Nx * g.Ny;
+    hipLaunchKernelGGL((moments_pass1<S, kMX>), dim3(blocks_for(n, 256)), dim3(256), 0, s, g, k,
+                       f, f0lo, T, scratch, rho, Tout);
+    hipLaunchKernelGGL(moments_pass2, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, k,
+                       (const double*)scratch, (const double*)rho, ux, uy);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_f32(const Grid& g, const Phys& k, const float* f, const float* f0lo,
+                              const float* T, double* scratch, double* rho, double* ux,
+                              double* uy, double* Tout, hipStream_t s) {
+    if (f0lo) return moments_impl<float, true>(g, k, f, f0lo, T, scratch, rho, ux, uy, Tout, s);
+    return moments_impl<float, false>(g, k, f, nullptr, T, scratch, rho, ux, uy, Tout, s);
+}
+hipError_t launch_moments_f64(const Grid& g, const Phys& k, const double* f, const double* T,
+                              double* scratch, double* rho, double* ux, double* uy,
+                              double* Tout, hipStream_t s) {
+    return moments_impl<double, false>(g, k, f, nullptr, T, scratch, rho, ux, uy, Tout, s);
+}
+
+hipError_t launch_init_f32(const Grid& g, const Phys& k, const double* rho0, float* f,
+                           float* f0lo, float* T, hipStream_t s) {
+    const int n = g.rows * g.Nx;
+    if (f0lo)
+        hipLaunchKernelGGL((init_kernel<float, true>), dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                           g, k, rho0, f, f0lo, T);
+    else
+        hipLaunchKernelGGL((init_kernel<float, false>), dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                           g, k, rho0, f, f0lo, T);
+    return hipGetLastError();
+}
+hipError_t launch_init_f64(const Grid& g, const Phys& k, const double* rho0, double* f,
+                           double* T, hipStream_t s) {
+    const int n = g.rows * g.Nx;
+    hipLaunchKernelGGL((init_kernel<double, false>), dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       g, k, rho0, f, (float*)nullptr, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* rho, const double* ux, const double* uy, const double* T,
+                         int n, double Cv, double* partials, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_pass1, dim3(kReduceBlocks), dim3(256), 0, s, rho, ux, uy, T, n, Cv,
+                       partials);
+    hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(64), 0, s, (const double*)partials,
+                       kReduceBlocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbmk

@@ -1,0 +1,708 @@
+// Host runtime of the C-ABI declared in include/lbm.h: parameter resolution
+// (Peng-Robinson critical point and coexistence, Eq. 11), memory layout,
+// launch shapes, the step loop, moments, reductions and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using lbmk::Grid;
+using lbmk::Phys;
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+lbm_status fail(lbm_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+// ---- Peng-Robinson thermodynamics (Eq. 11), host FP64 -------------------
+double kappa_of(double omega) { return 0.37464 + 1.54226 * omega - 0.26992 * omega * omega; }
+
+struct Eos {
+    double a, b, R, k, Tc;
+    double phi(double T) const {
+        const double s = 1.0 + k * (1.0 - std::sqrt(T / Tc));
+        return s * s;
+    }
+    double P(double r, double T) const {
+        const double br = b * r;
+        return r * R * T / (1.0 - br) - a * phi(T) * r * r / (1.0 + 2.0 * br - br * br);
+    }
+    double dPdr(double r, double T) const {
+        const double br = b * r, D = 1.0 + 2.0 * br - br * br;
+        return R * T / ((1.0 - br) * (1.0 - br)) - 2.0 * a * phi(T) * r * (1.0 + br) / (D * D);
+    }
+    // chemical potential from the Helmholtz free energy of Eq. 11:
+    // f = rho R T [ln(rho/(1 - b rho)) - 1]
+    //     - a phi rho / (2 sqrt2 b) ln[(1 + (1+sqrt2) b rho) / (1 + (1-sqrt2) b rho)],
+    // mu = df/drho (the additive constant drops out of equalities)
+    double mu(double r, double T) const {
+        const double br = b * r, s2 = std::sqrt(2.0);
+        const double L = std::log((1.0 + (1.0 + s2) * br) / (1.0 + (1.0 - s2) * br));
+        return R * T * (std::log(r / (1.0 - br)) + br / (1.0 - br)) -
+               a * phi(T) / (2.0 * s2 * b) * L - a * phi(T) * r / (1.0 + 2.0 * br - br * br);
+    }
+};
+
+// Critical point: on the spinodal (dP/drho = 0, phi = 1) T(eta), eta = b rho,
+// is proportional to eta (1+eta)(1-eta)^2 / (1+2eta-eta^2)^2; its maximum is
+// the zero of the logarithmic derivative, found by bisection.
+void critical_point(double a, double b, double R, double* rho_c, double* T_c) {
+    auto dlog = [](double e) {
+        return 1.0 / e + 1.0 / (1.0 + e) - 2.0 / (1.0 - e) -
+               2.0 * (2.0 - 2.0 * e) / (1.0 + 2.0 * e - e * e);
+    };
+    double lo = 1e-6, hi = 1.0 - 1e-6;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (dlog(mid) > 0.0) lo = mid; else hi = mid;
+    }
+    const double e = 0.5 * (lo + hi), D = 1.0 + 2.0 * e - e * e;
+    *rho_c = e / b;
+    *T_c = 2.0 * a / (b * R) * e * (1.0 + e) * (1.0 - e) * (1.0 - e) / (D * D);
+}
+
+template <class F>
+double bisect(F f, double lo, double hi) {
+    const double flo = f(lo);
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi), fm = f(mid);
+        if ((fm > 0.0) == (flo > 0.0)) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Coexistence at T: equal pressure and equal chemical potential.  For a trial
+// pressure p between the spinodal pressures the vapour and liquid roots of
+// P = p are bracketed; mu(liquid) - mu(vapour) changes sign at p_sat.
+bool coexistence(const Eos& E, double T, double* rg, double* rl, double* ps) {
+    const double rmax = 1.0 / E.b;
+    const int n = 4000;
+    double s1 = -1.0, s2 = -1.0;
+    double prev = E.dPdr(rmax * 1e-6, T);
+    for (int i = 1; i < n; ++i) {
+        const double r = rmax * i / n;
+        const double cur = E.dPdr(r, T);
+        if (prev > 0.0 && cur <= 0.0 && s1 < 0.0)
+            s1 = bisect([&](double x) { return E.dPdr(x, T); }, rmax * (i - 1) / n, r);
+        if (prev <= 0.0 && cur > 0.0 && s1 > 0.0)
+            s2 = bisect([&](double x) { return E.dPdr(x, T); }, rmax * (i - 1) / n, r);
+        prev = cur;
+    }
+    if (s1 < 0.0 || s2 < 0.0) return false;
+    const double pmax = E.P(s1, T), pmin = std::max(E.P(s2, T), 1e-300);
+    double g = 0, l = 0;
+    auto dmu = [&](double p) {
+        g = bisect([&](double x) { return E.P(x, T) - p; }, 1e-300, s1);
+        l = bisect([&](double x) { return E.P(x, T) - p; }, s2, rmax * (1.0 - 1e-15));
+        return E.mu(l, T) - E.mu(g, T);
+    };
+    const double p = bisect(dmu, pmin, pmax);
+    dmu(p);
+    *rg = g;
+    *rl = l;
+    *ps = p;
+    return true;
+}
+
+constexpr int kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int pitch, rows;
+    size_t plane, esz;
+    size_t off_f[2], off_lo[2], off_T[2], off_mom, off_scr, off_part, off_out, total;
+};
+
+bool make_layout(const lbm_params& p, Layout* L) {
+    const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
+    L->pitch = (p.Nx + 63) / 64 * 64;
+    L->rows = per ? p.Ny : p.Ny - 2;
+    L->plane = (size_t)L->pitch * L->rows;
+    L->esz = p.precision == LBM_FP64 ? 8 : 4;
+    if (9 * L->plane >= (size_t)1 << 32) return false;  // 32-bit element offsets
+    const size_t cells = (size_t)p.Nx * p.Ny;
+    size_t o = 0;
+    for (int b = 0; b < 2; ++b) {
+        L->off_f[b] = o;
+        o = align_up(o + 9 * L->plane * L->esz);
+    }
+    for (int b = 0; b < 2; ++b) {
+        L->off_lo[b] = o;
+        if (p.precision == LBM_FP32_DEV_MASSEXACT) o = align_up(o + L->plane * 4);
+    }
+    for (int b = 0; b < 2; ++b) {
+        L->off_T[b] = o;
+        o = align_up(o + L->plane * L->esz);
+    }
+    L->off_mom = o;
+    o = align_up(o + 4 * cells * sizeof(double));
+    L->off_scr = o;
+    o = align_up(o + 3 * cells * sizeof(double));
+    L->off_part = o;
+    o = align_up(o + lbmk::kReduceBlocks * 5 * sizeof(double));
+    L->off_out = o;
+    o = align_up(o + 8 * sizeof(double));
+    L->total = o;
+    return true;
+}
+
+lbm_status validate(const lbm_params& p) {
+    const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
+    if (p.Nx < 3) return fail(LBM_EINVAL, "Nx = %d < 3", p.Nx);
+    if (p.Ny < (per ? 3 : 4)) return fail(LBM_EINVAL, "Ny = %d too small", p.Ny);
+    if (p.precision < LBM_FP32_DEV || p.precision > LBM_FP32_DEV_MASSEXACT)
+        return fail(LBM_EINVAL, "unknown precision %d", p.precision);
+    if (p.flags & ~7u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.G == 0.0) return fail(LBM_EINVAL, "G must be nonzero");
+    const double rates[5] = {p.s_rho, p.s_e, p.s_zeta, p.s_j, p.s_q};
+    for (double s : rates)
+        if (!(s > 0.0 && s < 2.0)) return fail(LBM_EINVAL, "relaxation rate %g outside (0, 2)", s);
+    if (p.s_e != p.s_zeta) return fail(LBM_EINVAL, "Eq. 3 requires s_e == s_zeta");
+    if (!(p.tau_g > 0.5 && p.tau_l > 0.5)) return fail(LBM_EINVAL, "tau must exceed 1/2");
+    if (!(p.a > 0.0 && p.b > 0.0 && p.R > 0.0 && p.T_c > 0.0))
+        return fail(LBM_EINVAL, "EOS constants must be positive");
+    if (!(p.T_0 > 0.0 && p.T_w > 0.0)) return fail(LBM_EINVAL, "temperatures must be positive");
+    if (!(p.C_v > 0.0) || p.lambda < 0.0) return fail(LBM_EINVAL, "C_v > 0, lambda >= 0 needed");
+    if (!(p.rho_ref > 0.0)) return fail(LBM_EINVAL, "rho_ref must be positive");
+    Layout L;
+    if (!make_layout(p, &L)) return fail(LBM_EINVAL, "grid too large for 32-bit offsets");
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_sim {
+    lbm_params p;
+    Grid g;
+    Phys k;
+    Layout L;
+    int dev = 0;
+    char* base = nullptr;
+    bool owns_mem = false;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    int64_t n = 0;
+    int fcur = 0, tcur = 0;
+    int seg_rows = 0;
+
+    template <class S>
+    S* f(int b) const { return reinterpret_cast<S*>(base + L.off_f[b]); }
+    template <class S>
+    S* T(int b) const { return reinterpret_cast<S*>(base + L.off_T[b]); }
+    float* lo(int b) const {
+        return p.precision == LBM_FP32_DEV_MASSEXACT ? reinterpret_cast<float*>(base + L.off_lo[b])
+                                                     : nullptr;
+    }
+    double* mom(int q) const {
+        return reinterpret_cast<double*>(base + L.off_mom) + (size_t)q * p.Nx * p.Ny;
+    }
+    double* scr() const { return reinterpret_cast<double*>(base + L.off_scr); }
+    double* part() const { return reinterpret_cast<double*>(base + L.off_part); }
+    double* out() const { return reinterpret_cast<double*>(base + L.off_out); }
+};
+
+namespace {
+
+// default launch shape: enough waves to give each of the 1024 SIMDs about two
+// (the register budget of the fused kernel allows two resident per SIMD), but
+// segments of at least 16 rows so the 10 recomputed halo rows stay a minority.
+int default_seg_rows(const lbm_params& p, int rows) {
+    const int strips = (p.Nx + lbmk::kOwned - 1) / lbmk::kOwned;
+    const int want_units = 2048;
+    int segs = std::max(1, (want_units + strips - 1) / strips);
+    int sr = (rows + segs - 1) / segs;
+    sr = std::max(sr, std::min(16, rows));
+    return sr;
+}
+
+void set_grid(lbm_sim* s, int seg_rows) {
+    const lbm_params& p = s->p;
+    Grid& g = s->g;
+    g.Nx = p.Nx;
+    g.Ny = p.Ny;
+    g.pitch = s->L.pitch;
+    g.rows = s->L.rows;
+    g.periodic_y = (p.flags & LBM_PERIODIC_Y) ? 1 : 0;
+    g.y_first = g.periodic_y ? 0 : 1;
+    g.plane = (unsigned)s->L.plane;
+    g.n_strips = (p.Nx + lbmk::kOwned - 1) / lbmk::kOwned;
+    g.seg_rows = std::max(1, std::min(seg_rows, g.rows));
+    g.n_segs = (g.rows + g.seg_rows - 1) / g.seg_rows;
+    g.n_units = g.n_strips * g.n_segs;
+    const int nb = (g.n_units + lbmk::kWavesPerBlock - 1) / lbmk::kWavesPerBlock;
+    g.n_blocks_pad = (nb + 7) / 8 * 8;
+    s->seg_rows = g.seg_rows;
+}
+
+void set_phys(lbm_sim* s) {
+    const lbm_params& p = s->p;
+    Phys& k = s->k;
+    std::memset(&k, 0, sizeof(k));
+    const double kap = kappa_of(p.omega);
+    k.rho_ref = p.rho_ref;
+    k.T_ref = p.T_0;
+    k.dT_wall = p.T_w - p.T_0;
+    k.a = p.a;
+    k.b = p.b;
+    k.R = p.R;
+    k.kappa = kap;
+    k.inv_Tc = 1.0 / p.T_c;
+    k.inv_G = 1.0 / p.G;
+    k.negG = -p.G;
+    k.psi_wall_eff = p.psi_w * p.G_w / p.G;
+    k.Gw_psiw = p.G_w * p.psi_w;
+    k.c_e = 12.0 * p.theta / (1.0 / p.s_e - 0.5);
+    k.c_z = 12.0 * p.theta / (1.0 / p.s_zeta - 0.5);
+    k.s_rho = p.s_rho;
+    k.s_e = p.s_e;
+    k.s_z = p.s_zeta;
+    k.s_j = p.s_j;
+    k.s_q = p.s_q;
+    k.tau_g = p.tau_g;
+    k.dtau = p.tau_l - p.tau_g;
+    k.rho_g = p.rho_g;
+    k.inv_drho = (p.rho_l != p.rho_g) ? 1.0 / (p.rho_l - p.rho_g) : 0.0;
+    k.inv_Cv = 1.0 / p.C_v;
+    k.lambda = p.lambda;
+    k.g_x = p.g_x;
+    k.g_y = p.g_y;
+    k.rho_v = p.rho_v;
+    k.rkA = p.R;
+    k.rkB1 = p.a * kap * (1.0 + kap) / std::sqrt(p.T_c);
+    k.rkB2 = p.a * kap * kap / p.T_c;
+    k.flags = p.flags;
+}
+
+double drive_at(const lbm_params& p, int64_t n) {
+    if (!(p.period > 0.0)) return 0.0;
+    return p.g_osc * std::sin(2.0 * M_PI * (double)n / p.period);
+}
+
+hipError_t enqueue_step(lbm_sim* s) {
+    s->k.drive = drive_at(s->p, s->n);
+    const int fa = s->fcur, fb = 1 - s->fcur;
+    const int ta = s->tcur, tb = (s->p.flags & LBM_FREEZE_T) ? s->tcur : 1 - s->tcur;
+    hipError_t e;
+    if (s->p.precision == LBM_FP64) {
+        lbmk::Bufs<double> b{s->f<double>(fa), s->f<double>(fb), nullptr, nullptr,
+                             s->T<double>(ta), s->T<double>(tb)};
+        e = lbmk::launch_step_f64(s->g, s->k, b, s->stream);
+    } else {
+        lbmk::Bufs<float> b{s->f<float>(fa), s->f<float>(fb), s->lo(fa), s->lo(fb),
+                            s->T<float>(ta), s->T<float>(tb)};
+        e = lbmk::launch_step_f32(s->g, s->k, b, s->p.precision == LBM_FP32_DEV_MASSEXACT,
+                                  s->stream);
+    }
+    if (e != hipSuccess) return e;
+    s->fcur = fb;
+    s->tcur = tb;
+    s->n += 1;
+    return hipSuccess;
+}
+
+hipError_t enqueue_moments(lbm_sim* s) {
+    s->k.drive = drive_at(s->p, s->n);
+    if (s->p.precision == LBM_FP64)
+        return lbmk::launch_moments_f64(s->g, s->k, s->f<double>(s->fcur), s->T<double>(s->tcur),
+                                        s->scr(), s->mom(0), s->mom(1), s->mom(2), s->mom(3),
+                                        s->stream);
+    return lbmk::launch_moments_f32(s->g, s->k, s->f<float>(s->fcur), s->lo(s->fcur),
+                                    s->T<float>(s->tcur), s->scr(), s->mom(0), s->mom(1),
+                                    s->mom(2), s->mom(3), s->stream);
+}
+
+size_t state_payload(const lbm_sim* s) {
+    size_t b = 9 * s->L.plane * s->L.esz + s->L.plane * s->L.esz;
+    if (s->p.precision == LBM_FP32_DEV_MASSEXACT) b += s->L.plane * 4;
+    return b;
+}
+
+struct CkptHeader {
+    char magic[8];
+    int64_t n;
+    lbm_params p;
+};
+
+}  // namespace
+
+extern "C" {
+
+void lbm_params_default(lbm_params* p) {
+    std::memset(p, 0, sizeof(*p));
+    p->Nx = 128;
+    p->Ny = 32;
+    p->a = 3.0 / 49.0;
+    p->b = 2.0 / 21.0;
+    p->R = 1.0;
+    p->omega = 0.344;
+    p->T_c = 0.0;
+    p->G = -1.0;
+    p->theta = 0.104;
+    p->G_w = 0.0;
+    p->psi_w = 0.0;
+    p->s_rho = 1.0;
+    p->s_e = 0.8;
+    p->s_zeta = 0.8;
+    p->s_j = 1.0;
+    p->s_q = 1.1;
+    p->tau_g = 1.0;
+    p->tau_l = 1.0;
+    p->C_v = 5.0;
+    p->lambda = 0.25;
+    p->g_osc = 1e-6;
+    p->period = 2000.0;
+    p->precision = LBM_FP32_DEV;
+    p->flags = 0;
+}
+
+lbm_status lbm_eos_critical(double a, double b, double R, double* rho_c, double* T_c) {
+    if (!(a > 0 && b > 0 && R > 0) || !rho_c || !T_c)
+        return fail(LBM_EINVAL, "EOS constants must be positive");
+    critical_point(a, b, R, rho_c, T_c);
+    return LBM_OK;
+}
+
+lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_g, double* rho_l,
+                               double* p_sat) {
+    if (!p || !rho_g || !rho_l || !p_sat) return fail(LBM_EINVAL, "null argument");
+    double Tc = p->T_c, rc;
+    if (!(Tc > 0.0)) critical_point(p->a, p->b, p->R, &rc, &Tc);
+    if (!(T > 0.0 && T < Tc)) return fail(LBM_EINVAL, "T = %g is not below Tc = %g", T, Tc);
+    Eos E{p->a, p->b, p->R, kappa_of(p->omega), Tc};
+    if (!coexistence(E, T, rho_g, rho_l, p_sat))
+        return fail(LBM_EINVAL, "no coexistence found at T = %g", T);
+    return LBM_OK;
+}
+
+lbm_status lbm_params_resolve(lbm_params* p) {
+    if (!p) return fail(LBM_EINVAL, "null params");
+    if (!(p->a > 0 && p->b > 0 && p->R > 0)) return fail(LBM_EINVAL, "EOS constants must be positive");
+    if (!(p->T_c > 0.0)) {
+        double rc;
+        critical_point(p->a, p->b, p->R, &rc, &p->T_c);
+    }
+    if (!(p->T_0 > 0.0)) p->T_0 = 0.86 * p->T_c;
+    if (!(p->T_w > 0.0)) p->T_w = 0.80 * p->T_c;
+    if (!(p->rho_g > 0.0) || !(p->rho_l > 0.0) || !(p->rho_v > 0.0)) {
+        double g, l, ps;
+        lbm_status st = lbm_eos_coexistence(p, p->T_0, &g, &l, &ps);
+        if (st != LBM_OK) return st;
+        if (!(p->rho_g > 0.0)) p->rho_g = g;
+        if (!(p->rho_l > 0.0)) p->rho_l = l;
+        if (!(p->rho_v > 0.0)) p->rho_v = g;
+    }
+    if (!(p->rho_ref > 0.0)) p->rho_ref = p->rho_v;
+    return LBM_OK;
+}
+
+size_t lbm_workspace_bytes(const lbm_params* pin) {
+    if (!pin) return 0;
+    lbm_params p = *pin;
+    if (lbm_params_resolve(&p) != LBM_OK || validate(p) != LBM_OK) return 0;
+    Layout L;
+    make_layout(p, &L);
+    return L.total;
+}
+
+lbm_status lbm_create(const lbm_params* pin, const double* rho0, void* workspace,
+                      size_t ws_bytes, void* stream, lbm_sim** out) {
+    if (!out) return fail(LBM_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!pin) return fail(LBM_EINVAL, "null params");
+    lbm_params p = *pin;
+    lbm_status st = lbm_params_resolve(&p);
+    if (st != LBM_OK) return st;
+    st = validate(p);
+    if (st != LBM_OK) return st;
+    const size_t cells = (size_t)p.Nx * p.Ny;
+    const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
+    std::vector<double> r0(cells, p.rho_v);
+    if (rho0) std::copy(rho0, rho0 + cells, r0.begin());
+    for (int y = per ? 0 : 1; y < (per ? p.Ny : p.Ny - 1); ++y)
+        for (int x = 0; x < p.Nx; ++x) {
+            const double r = r0[(size_t)y * p.Nx + x];
+            if (!(r > 0.0 && p.b * r < 1.0))
+                return fail(LBM_EINVAL, "initial density %g at (%d, %d) outside (0, 1/b)", r, x, y);
+        }
+
+    lbm_sim* s = new (std::nothrow) lbm_sim();
+    if (!s) return fail(LBM_ENOMEM, "host allocation failed");
+    s->p = p;
+    make_layout(p, &s->L);
+    hipError_t e = hipGetDevice(&s->dev);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(LBM_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    if (workspace) {
+        if (ws_bytes < s->L.total || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) {
+            delete s;
+            return fail(LBM_EINVAL, "workspace needs %zu bytes aligned to %d", s->L.total, kAlign);
+        }
+        s->base = static_cast<char*>(workspace);
+    } else {
+        e = hipMalloc(reinterpret_cast<void**>(&s->base), s->L.total);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(LBM_ENOMEM, "hipMalloc(%zu): %s", s->L.total, hipGetErrorString(e));
+        }
+        s->owns_mem = true;
+    }
+    if (stream) {
+        s->stream = static_cast<hipStream_t>(stream);
+    } else {
+        e = hipStreamCreate(&s->stream);
+        if (e != hipSuccess) {
+            lbm_destroy(s);
+            return fail(LBM_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        s->owns_stream = true;
+    }
+    set_phys(s);
+    set_grid(s, default_seg_rows(p, s->L.rows));
+    // zero everything (pitch padding stays zero), upload rho0, start state
+    e = hipMemsetAsync(s->base, 0, s->L.total, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->mom(0), r0.data(), cells * sizeof(double), hipMemcpyHostToDevice,
+                           s->stream);
+    if (e == hipSuccess) {
+        if (p.precision == LBM_FP64)
+            e = lbmk::launch_init_f64(s->g, s->k, s->mom(0), s->f<double>(0), s->T<double>(0),
+                                      s->stream);
+        else
+            e = lbmk::launch_init_f32(s->g, s->k, s->mom(0), s->f<float>(0), s->lo(0),
+                                      s->T<float>(0), s->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // r0 must outlive the copy
+    if (e != hipSuccess) {
+        lbm_destroy(s);
+        return fail(LBM_EDEVICE, "initialisation: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_sim* s, int64_t n) {
+    if (!s) return fail(LBM_EINVAL, "null sim");
+    if (n < 0) return fail(LBM_EINVAL, "negative step count");
+    HIPCHK(hipSetDevice(s->dev));
+    for (int64_t i = 0; i < n; ++i) HIPCHK(enqueue_step(s));
+    return LBM_OK;
+}
+
+lbm_status lbm_synchronize(lbm_sim* s) {
+    if (!s) return fail(LBM_EINVAL, "null sim");
+    HIPCHK(hipSetDevice(s->dev));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_sim* s, double* rho, double* ux, double* uy, double* T) {
+    if (!s) return fail(LBM_EINVAL, "null sim");
+    HIPCHK(hipSetDevice(s->dev));
+    HIPCHK(enqueue_moments(s));
+    double* outs[4] = {rho, ux, uy, T};
+    const size_t bytes = (size_t)s->p.Nx * s->p.Ny * sizeof(double);
+    for (int q = 0; q < 4; ++q)
+        if (outs[q])
+            HIPCHK(hipMemcpyAsync(outs[q], s->mom(q), bytes, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_reduce(lbm_sim* s, double out[5]) {
+    if (!s || !out) return fail(LBM_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(s->dev));
+    HIPCHK(enqueue_moments(s));
+    HIPCHK(lbmk::launch_reduce(s->mom(0), s->mom(1), s->mom(2), s->mom(3), s->p.Nx * s->p.Ny,
+                               s->p.C_v, s->part(), s->out(), s->stream));
+    HIPCHK(hipMemcpyAsync(out, s->out(), 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (out[4] > 0.0) return fail(LBM_EUNSTABLE, "%g non-finite nodes at n = %lld", out[4],
+                                  (long long)s->n);
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_sim* s) {
+    if (!s) return LBM_OK;
+    hipSetDevice(s->dev);
+    if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->owns_mem && s->base) hipFree(s->base);
+    if (s->owns_stream && s->stream) hipStreamDestroy(s->stream);
+    delete s;
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_sim* s) { return s ? s->n : -1; }
+
+lbm_status lbm_get_params(const lbm_sim* s, lbm_params* out) {
+    if (!s || !out) return fail(LBM_EINVAL, "null argument");
+    *out = s->p;
+    return LBM_OK;
+}
+
+const char* lbm_last_error(void) { return g_err; }
+
+size_t lbm_state_bytes(const lbm_sim* s) {
+    return s ? sizeof(CkptHeader) + state_payload(s) : 0;
+}
+
+lbm_status lbm_save(lbm_sim* s, void* host, size_t bytes) {
+    if (!s || !host) return fail(LBM_EINVAL, "null argument");
+    if (bytes < lbm_state_bytes(s)) return fail(LBM_EINVAL, "buffer too small");
+    HIPCHK(hipSetDevice(s->dev));
+    CkptHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, "LBMCKPT1", 8);
+    h.n = s->n;
+    h.p = s->p;
+    char* dst = static_cast<char*>(host);
+    std::memcpy(dst, &h, sizeof(h));
+    dst += sizeof(h);
+    const size_t fb = 9 * s->L.plane * s->L.esz, tb = s->L.plane * s->L.esz;
+    HIPCHK(hipMemcpyAsync(dst, s->base + s->L.off_f[s->fcur], fb, hipMemcpyDeviceToHost, s->stream));
+    dst += fb;
+    HIPCHK(hipMemcpyAsync(dst, s->base + s->L.off_T[s->tcur], tb, hipMemcpyDeviceToHost, s->stream));
+    dst += tb;
+    if (s->p.precision == LBM_FP32_DEV_MASSEXACT)
+        HIPCHK(hipMemcpyAsync(dst, s->base + s->L.off_lo[s->fcur], s->L.plane * 4,
+                              hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_sim* s, const void* host, size_t bytes) {
+    if (!s || !host) return fail(LBM_EINVAL, "null argument");
+    if (bytes < lbm_state_bytes(s)) return fail(LBM_EINVAL, "buffer too small");
+    CkptHeader h;
+    std::memcpy(&h, host, sizeof(h));
+    if (std::memcmp(h.magic, "LBMCKPT1", 8) != 0) return fail(LBM_EINVAL, "not a checkpoint");
+    if (h.p.Nx != s->p.Nx || h.p.Ny != s->p.Ny || h.p.precision != s->p.precision ||
+        (h.p.flags & LBM_PERIODIC_Y) != (s->p.flags & LBM_PERIODIC_Y))
+        return fail(LBM_EINVAL, "checkpoint grid or precision differs");
+    HIPCHK(hipSetDevice(s->dev));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const char* src = static_cast<const char*>(host) + sizeof(h);
+    const size_t fb = 9 * s->L.plane * s->L.esz, tb = s->L.plane * s->L.esz;
+    HIPCHK(hipMemcpyAsync(s->base + s->L.off_f[s->fcur], src, fb, hipMemcpyHostToDevice, s->stream));
+    src += fb;
+    HIPCHK(hipMemcpyAsync(s->base + s->L.off_T[s->tcur], src, tb, hipMemcpyHostToDevice, s->stream));
+    src += tb;
+    if (s->p.precision == LBM_FP32_DEV_MASSEXACT)
+        HIPCHK(hipMemcpyAsync(s->base + s->L.off_lo[s->fcur], src, s->L.plane * 4,
+                              hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const int seg = s->seg_rows;
+    s->p = h.p;
+    s->n = h.n;
+    set_phys(s);
+    set_grid(s, seg);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_sim* s, int32_t seg_rows) {
+    if (!s) return fail(LBM_EINVAL, "null sim");
+    set_grid(s, seg_rows > 0 ? seg_rows : default_seg_rows(s->p, s->L.rows));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_launch(const lbm_sim* s, int32_t* seg_rows, int32_t* waves) {
+    if (!s) return fail(LBM_EINVAL, "null sim");
+    if (seg_rows) *seg_rows = s->g.seg_rows;
+    if (waves) *waves = s->g.n_units;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_sim* s, int32_t steps_per_trial, double* best_ms) {
+    if (!s) return fail(LBM_EINVAL, "null sim");
+    if (steps_per_trial < 1) steps_per_trial = 10;
+    HIPCHK(hipSetDevice(s->dev));
+    // snapshot the state on the device; every trial restarts from it
+    const size_t fb = 9 * s->L.plane * s->L.esz, tb = s->L.plane * s->L.esz;
+    const size_t lb = s->p.precision == LBM_FP32_DEV_MASSEXACT ? s->L.plane * 4 : 0;
+    char* snap = nullptr;
+    HIPCHK(hipMalloc(reinterpret_cast<void**>(&snap), fb + tb + lb));
+    const int64_t n0 = s->n;
+    const int f0 = s->fcur, t0 = s->tcur;
+    auto restore = [&]() -> hipError_t {
+        s->n = n0;
+        s->fcur = f0;
+        s->tcur = t0;
+        hipError_t e = hipMemcpyAsync(s->base + s->L.off_f[f0], snap, fb, hipMemcpyDeviceToDevice,
+                                      s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->base + s->L.off_T[t0], snap + fb, tb, hipMemcpyDeviceToDevice,
+                               s->stream);
+        if (e == hipSuccess && lb)
+            e = hipMemcpyAsync(s->base + s->L.off_lo[f0], snap + fb + tb, lb,
+                               hipMemcpyDeviceToDevice, s->stream);
+        return e;
+    };
+    hipError_t e = hipMemcpyAsync(snap, s->base + s->L.off_f[f0], fb, hipMemcpyDeviceToDevice,
+                                  s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(snap + fb, s->base + s->L.off_T[t0], tb, hipMemcpyDeviceToDevice,
+                           s->stream);
+    if (e == hipSuccess && lb)
+        e = hipMemcpyAsync(snap + fb + tb, s->base + s->L.off_lo[f0], lb, hipMemcpyDeviceToDevice,
+                           s->stream);
+    std::vector<int> cands;
+    for (int c : {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128, 192, 256, 512})
+        if (c <= s->L.rows) cands.push_back(c);
+    cands.push_back(s->L.rows);
+    cands.push_back(default_seg_rows(s->p, s->L.rows));
+    std::sort(cands.begin(), cands.end());
+    cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    double best = 1e300;
+    int best_seg = s->seg_rows;
+    for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
+        set_grid(s, cands[ci]);
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = enqueue_step(s);
+        if (e == hipSuccess) e = hipEventRecord(ev0, s->stream);
+        for (int i = 0; i < steps_per_trial && e == hipSuccess; ++i) e = enqueue_step(s);
+        if (e == hipSuccess) e = hipEventRecord(ev1, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        if (e == hipSuccess && ms / steps_per_trial < best) {
+            best = ms / steps_per_trial;
+            best_seg = cands[ci];
+        }
+        if (e == hipSuccess) e = restore();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    hipFree(snap);
+    set_grid(s, best_seg);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    if (best_ms) *best_ms = best;
+    return LBM_OK;
+}
+
+}  // extern "C"

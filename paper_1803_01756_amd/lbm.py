@@ -1,0 +1,295 @@
+"""Python binding of the C-ABI in ``include/lbm.h`` (ctypes, argument
+marshalling only).  Every step of the method runs in the HIP library
+``liblbm_hip.so``; when that library is missing or cannot be loaded, the
+calls raise instead of falling back to anything else.
+
+The functions keep the C names (``lbm_create``, ``lbm_step``, ...); ``Sim``
+wraps them for convenience and can take its device memory and stream from
+PyTorch.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblbm_hip.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_FP32_DEV, LBM_FP64, LBM_FP32_DEV_MASSEXACT = 0, 1, 2
+LBM_FREEZE_T, LBM_SINGLE_PHASE, LBM_PERIODIC_Y = 1, 2, 4
+
+_STATUS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EDEVICE: "EDEVICE",
+           LBM_EUNSTABLE: "EUNSTABLE", LBM_ESTATE: "ESTATE"}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class lbm_params(C.Structure):
+    _fields_ = [
+        ("Nx", C.c_int32), ("Ny", C.c_int32),
+        ("a", C.c_double), ("b", C.c_double), ("R", C.c_double), ("omega", C.c_double),
+        ("T_c", C.c_double), ("G", C.c_double), ("theta", C.c_double),
+        ("G_w", C.c_double), ("psi_w", C.c_double),
+        ("s_rho", C.c_double), ("s_e", C.c_double), ("s_zeta", C.c_double),
+        ("s_j", C.c_double), ("s_q", C.c_double),
+        ("tau_g", C.c_double), ("tau_l", C.c_double),
+        ("rho_g", C.c_double), ("rho_l", C.c_double),
+        ("C_v", C.c_double), ("lambda_", C.c_double),
+        ("T_0", C.c_double), ("T_w", C.c_double),
+        ("g_osc", C.c_double), ("period", C.c_double),
+        ("g_x", C.c_double), ("g_y", C.c_double), ("rho_v", C.c_double),
+        ("rho_ref", C.c_double),
+        ("precision", C.c_int32), ("flags", C.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is not built; run "
+                               "`python -m paper_1803_01756_amd.build`" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER(lbm_params)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        sig = {
+            "lbm_params_default": (None, [P]),
+            "lbm_params_resolve": (C.c_int, [P]),
+            "lbm_eos_critical": (C.c_int, [C.c_double, C.c_double, C.c_double, dp, dp]),
+            "lbm_eos_coexistence": (C.c_int, [P, C.c_double, dp, dp, dp]),
+            "lbm_workspace_bytes": (C.c_size_t, [P]),
+            "lbm_create": (C.c_int, [P, dp, vp, C.c_size_t, vp, C.POINTER(vp)]),
+            "lbm_step": (C.c_int, [vp, C.c_int64]),
+            "lbm_moments": (C.c_int, [vp, dp, dp, dp, dp]),
+            "lbm_reduce": (C.c_int, [vp, dp]),
+            "lbm_synchronize": (C.c_int, [vp]),
+            "lbm_destroy": (C.c_int, [vp]),
+            "lbm_time": (C.c_int64, [vp]),
+            "lbm_get_params": (C.c_int, [vp, P]),
+            "lbm_last_error": (C.c_char_p, []),
+            "lbm_state_bytes": (C.c_size_t, [vp]),
+            "lbm_save": (C.c_int, [vp, vp, C.c_size_t]),
+            "lbm_load": (C.c_int, [vp, vp, C.c_size_t]),
+            "lbm_set_launch": (C.c_int, [vp, C.c_int32]),
+            "lbm_get_launch": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+            "lbm_autotune": (C.c_int, [vp, C.c_int32, dp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names the header declares; the CPU tests check the library has them."""
+    return ["lbm_params_default", "lbm_params_resolve", "lbm_eos_critical",
+            "lbm_eos_coexistence", "lbm_workspace_bytes", "lbm_create", "lbm_step",
+            "lbm_moments", "lbm_reduce", "lbm_synchronize", "lbm_destroy", "lbm_time",
+            "lbm_get_params", "lbm_last_error", "lbm_state_bytes", "lbm_save", "lbm_load",
+            "lbm_set_launch", "lbm_get_launch", "lbm_autotune"]
+
+
+def _check(st: int):
+    if st != LBM_OK:
+        raise LBMError(st, lib().lbm_last_error().decode())
+
+
+def _dp(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ---- thin wrappers with the C names ----------------------------------------
+def lbm_params_default(**overrides) -> lbm_params:
+    p = lbm_params()
+    lib().lbm_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, "lambda_" if k == "lambda" else k, v)
+    return p
+
+
+def lbm_params_resolve(p: lbm_params) -> lbm_params:
+    q = lbm_params.from_buffer_copy(p)
+    _check(lib().lbm_params_resolve(C.byref(q)))
+    return q
+
+
+def lbm_eos_critical(a=3.0 / 49.0, b=2.0 / 21.0, R=1.0):
+    rc, tc = C.c_double(), C.c_double()
+    _check(lib().lbm_eos_critical(a, b, R, C.byref(rc), C.byref(tc)))
+    return rc.value, tc.value
+
+
+def lbm_eos_coexistence(p: lbm_params, T: float):
+    g, l, ps = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().lbm_eos_coexistence(C.byref(p), T, C.byref(g), C.byref(l), C.byref(ps)))
+    return g.value, l.value, ps.value
+
+
+def lbm_workspace_bytes(p: lbm_params) -> int:
+    return int(lib().lbm_workspace_bytes(C.byref(p)))
+
+
+def lbm_create(p: lbm_params, rho0=None, workspace: int = 0, ws_bytes: int = 0,
+               stream: int = 0) -> int:
+    h = C.c_void_p()
+    r = None
+    if rho0 is not None:
+        r = np.ascontiguousarray(rho0, dtype=np.float64)
+        if r.size != p.Nx * p.Ny:
+            raise ValueError("rho0 must have Nx*Ny entries")
+    _check(lib().lbm_create(C.byref(p), _dp(r), C.c_void_p(workspace or None), ws_bytes,
+                            C.c_void_p(stream or None), C.byref(h)))
+    return h.value
+
+
+def lbm_step(h: int, n: int):
+    _check(lib().lbm_step(C.c_void_p(h), int(n)))
+
+
+def lbm_moments(h: int, Nx: int, Ny: int):
+    outs = [np.empty((Ny, Nx)) for _ in range(4)]
+    _check(lib().lbm_moments(C.c_void_p(h), *[_dp(o) for o in outs]))
+    return tuple(outs)
+
+
+def lbm_reduce(h: int, check: bool = True):
+    out = np.zeros(5)
+    st = lib().lbm_reduce(C.c_void_p(h), _dp(out))
+    if check or st != LBM_EUNSTABLE:
+        _check(st)
+    return out
+
+
+def lbm_synchronize(h: int):
+    _check(lib().lbm_synchronize(C.c_void_p(h)))
+
+
+def lbm_destroy(h: int):
+    _check(lib().lbm_destroy(C.c_void_p(h)))
+
+
+def lbm_time(h: int) -> int:
+    return int(lib().lbm_time(C.c_void_p(h)))
+
+
+def lbm_get_params(h: int) -> lbm_params:
+    p = lbm_params()
+    _check(lib().lbm_get_params(C.c_void_p(h), C.byref(p)))
+    return p
+
+
+def lbm_save(h: int) -> bytes:
+    n = int(lib().lbm_state_bytes(C.c_void_p(h)))
+    buf = C.create_string_buffer(n)
+    _check(lib().lbm_save(C.c_void_p(h), buf, n))
+    return buf.raw
+
+
+def lbm_load(h: int, blob: bytes):
+    buf = C.create_string_buffer(blob, len(blob))
+    _check(lib().lbm_load(C.c_void_p(h), buf, len(blob)))
+
+
+def lbm_set_launch(h: int, seg_rows: int):
+    _check(lib().lbm_set_launch(C.c_void_p(h), int(seg_rows)))
+
+
+def lbm_get_launch(h: int):
+    s, w = C.c_int32(), C.c_int32()
+    _check(lib().lbm_get_launch(C.c_void_p(h), C.byref(s), C.byref(w)))
+    return s.value, w.value
+
+
+def lbm_autotune(h: int, steps_per_trial: int = 10) -> float:
+    ms = C.c_double()
+    _check(lib().lbm_autotune(C.c_void_p(h), int(steps_per_trial), C.byref(ms)))
+    return ms.value
+
+
+class Sim:
+    """One simulation.  With ``torch_memory=True`` the device workspace is a
+    torch tensor and the work is ordered on torch's current stream."""
+
+    def __init__(self, params: lbm_params, rho0=None, torch_memory: bool = False):
+        self._ws = None
+        ws_ptr, ws_bytes, stream = 0, 0, 0
+        if torch_memory:
+            import torch
+            ws_bytes = lbm_workspace_bytes(params)
+            if ws_bytes == 0:
+                raise LBMError(LBM_EINVAL, lib().lbm_last_error().decode())
+            self._ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+            ws_ptr = self._ws.data_ptr()
+            stream = torch.cuda.current_stream().cuda_stream
+        self.h = lbm_create(params, rho0, ws_ptr, ws_bytes, stream)
+        self.params = lbm_get_params(self.h)
+        self.Nx, self.Ny = self.params.Nx, self.params.Ny
+
+    def step(self, n: int = 1):
+        lbm_step(self.h, n)
+
+    def moments(self):
+        """(rho, ux, uy, T) as float64 [Ny, Nx] host arrays."""
+        return lbm_moments(self.h, self.Nx, self.Ny)
+
+    def reduce(self, check: bool = True):
+        return lbm_reduce(self.h, check)
+
+    def synchronize(self):
+        lbm_synchronize(self.h)
+
+    @property
+    def n(self) -> int:
+        return lbm_time(self.h)
+
+    def save(self) -> bytes:
+        return lbm_save(self.h)
+
+    def load(self, blob: bytes):
+        lbm_load(self.h, blob)
+
+    def set_launch(self, seg_rows: int):
+        lbm_set_launch(self.h, seg_rows)
+
+    def launch(self):
+        return lbm_get_launch(self.h)
+
+    def autotune(self, steps_per_trial: int = 10) -> float:
+        return lbm_autotune(self.h, steps_per_trial)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,82 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports every entry
+point that include/lbm.h declares, and the host-side parameter logic
+(resolution, validation, EOS solvers) works without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1803_01756_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_1803_01756_amd import build
+        build.build()
+    return lbm.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "lbm_create" in names and "lbm_step" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_names_match_header():
+    assert set(lbm.exported_symbols()) <= set(_declared())
+
+
+def test_params_default_and_resolve(L, orc):
+    p = lbm.lbm_params_resolve(lbm.lbm_params_default())
+    _, tc = orc.critical()
+    assert abs(p.T_c / tc - 1) < 1e-12
+    op = orc.default_params()
+    g, l, _ = orc.maxwell(op, 0.86 * tc)
+    assert abs(p.rho_g / g - 1) < 1e-10 and abs(p.rho_l / l - 1) < 1e-10
+    assert p.rho_v == p.rho_g and p.rho_ref == p.rho_v
+    assert abs(p.T_0 - 0.86 * tc) < 1e-15 and abs(p.T_w - 0.80 * tc) < 1e-15
+
+
+@pytest.mark.parametrize("frac", [0.56, 0.65, 0.78, 0.9])
+def test_library_coexistence_matches_oracle(L, orc, frac):
+    p = lbm.lbm_params_resolve(lbm.lbm_params_default())
+    g1, l1, p1 = lbm.lbm_eos_coexistence(p, frac * p.T_c)
+    g2, l2, p2 = orc.maxwell(orc.default_params(), frac * p.T_c)
+    assert abs(g1 / g2 - 1) < 1e-9 and abs(l1 / l2 - 1) < 1e-9 and abs(p1 / p2 - 1) < 1e-9
+
+
+@pytest.mark.parametrize("bad", [dict(Nx=2), dict(Ny=3), dict(s_e=0.9), dict(s_q=2.0),
+                                 dict(tau_g=0.5), dict(G=0.0), dict(precision=7),
+                                 dict(flags=64)])
+def test_workspace_bytes_rejects_invalid(L, bad):
+    p = lbm.lbm_params_default(**bad)
+    assert lbm.lbm_workspace_bytes(p) == 0
+    assert len(lbm.lib().lbm_last_error()) > 0
+
+
+def test_workspace_bytes_layout(L):
+    p = lbm.lbm_params_default(Nx=100, Ny=10)
+    n32 = lbm.lbm_workspace_bytes(p)
+    p.precision = lbm.LBM_FP64
+    n64 = lbm.lbm_workspace_bytes(p)
+    p.precision = lbm.LBM_FP32_DEV_MASSEXACT
+    nmx = lbm.lbm_workspace_bytes(p)
+    pitch, rows = 128, 8
+    pops = 2 * 9 * pitch * rows
+    assert n64 - n32 >= 4 * (pops + 2 * pitch * rows) - 256 * 8
+    assert nmx - n32 >= 2 * 4 * pitch * rows
