@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Throughput of the fused FP32 pseudopotential MRT-LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the 8192 x 512 plate channel (4.18 M fluid nodes), FP32 deviation
+storage, cold plates at 0.78 Tc with a 75 degree wall, drive amplitude 2e-6
+and period 4000 steps, saturated vapour with +-1 % seeded noise.  It is the
+HBM-bound configuration: its 2 x 36 B populations + 2 x 4 B temperature per
+node (352 MB) exceed the 256 MB Infinity Cache.  One step = one launch of the
+fused kernel over the whole channel.  Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line.  `value` is MLUPS (million fluid-node updates per
+second).  `roofline` compares the algorithmic bytes of one launch (80 B per
+node: 9 FP32 populations read and written, T read and written) per average
+launch time with the 8 TB/s HBM peak; `traffic` is the HBM traffic the
+rocprofv3 FETCH_SIZE / WRITE_SIZE counters measured for the same kernel
+(committed under profiles/), scaled by what those counters read for a plain
+copy of known size, or null when the kernel source changed since.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = {0: 80.0, 1: 160.0, 2: 88.0}  # FP32_DEV, FP64, FP32_DEV_MASSEXACT
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_step_8192x512_fp32.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1803_01756_amd", "csrc", "lbm_kernels.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per launch from the committed counter summary, or None."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    with open(PMC_FILE) as fh:
+        d = json.load(fh)
+    if d.get("source_sha256") != kernel_sha():
+        return None
+    fetch = d["fetch_kib_per_dispatch"] * 1024.0 / d["copy_fetch_factor"]
+    write = d["write_kib_per_dispatch"] * 1024.0 / d["copy_write_factor"]
+    return fetch + write
+
+
+def time_steps(sim, steps, warmup):
+    import torch
+    sim.step(warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1), wall * 1e3
+
+
+def fluid_nodes(p):
+    return p.Nx * (p.Ny if (p.flags & 4) else p.Ny - 2)
+
+
+def run_config(p, rho0, steps, warmup, tune=True, seg_rows=0):
+    from paper_1803_01756_amd import lbm
+    sim = lbm.Sim(p, rho0, torch_memory=True)
+    if seg_rows > 0:
+        sim.set_launch(seg_rows)
+    elif tune:
+        sim.autotune(10)
+    ms, wall_ms = time_steps(sim, steps, warmup)
+    seg, waves = sim.launch()
+    red = sim.reduce(check=False)
+    sim.close()
+    return ms, wall_ms, seg, waves, red
+
+
+def oracle_mlups(p, rho0, steps):
+    """FP64 oracle (single thread, as built) on the full grid for `steps`."""
+    from oracle import oracle as O
+    names = dict(T_c="Tc", G_w="Gw", psi_w="psiw", C_v="Cv", lambda_="lam", T_0="T0",
+                 T_w="Tw", g_x="gx", g_y="gy")
+    op = O.make_params(**{names.get(k, k): v for k, v in p.as_dict().items()
+                          if k not in ("rho_ref", "precision")})
+    sim = O.Sim(op, rho0)
+    sim.step(1)  # first-touch of the scratch fields outside the timing
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    return fluid_nodes(p) * steps / dt / 1e6, dt
+
+
+def batch_and_serve(args):
+    """64 channels of uneven size in one pool vs the same channels run one
+    after another alone; then a Poisson stream of requests served with
+    continuous batching."""
+    from paper_1803_01756_amd import inputs, lbm, serve
+    chans = [serve.channel_request(d, args.batch_steps)
+             for d in inputs.sample_channels(64, seed=1803)]
+    lups = sum(serve.lup(p, args.batch_steps) for p, _ in chans)
+    log("batched: 64 channels x %d steps (%.2e node updates)" % (args.batch_steps, lups))
+    tb, _ = serve.run_batch(chans, args.batch_steps, chunk=1000)
+    log("batched %.3f s; now the same channels one after another" % tb)
+    ta, _ = serve.run_alone(chans, args.batch_steps)
+    batched = dict(channels=64, steps=args.batch_steps, node_updates=lups,
+                   seconds=round(tb, 4), mlups=round(lups / tb / 1e6, 1),
+                   sims_per_s=round(64 / tb, 3),
+                   alone_seconds=round(ta, 4), alone_mlups=round(lups / ta / 1e6, 1),
+                   speedup_vs_alone=round(ta / tb, 3))
+    n_warm = 10
+    reqs = serve.make_requests(args.serve_requests, args.serve_rate)
+    log("served: %d requests at %.0f/s (first %d are warm-up)" % (len(reqs), args.serve_rate,
+                                                                   n_warm))
+    pool = lbm.Pool(200 << 30)
+    serve.serve(reqs, pool, chunk=500)
+    pool.close()
+    meas = reqs[n_warm:]
+    st = serve.latency_stats(meas)
+    lu = sum(serve.lup(r.params, r.steps) for r in meas)
+    served = dict(requests=len(meas), warmup_requests=n_warm, rate_per_s=args.serve_rate,
+                  cap_bytes=200 << 30, chunk_steps=500,
+                  p50_latency_s=round(st["p50_s"], 4), p99_latency_s=round(st["p99_s"], 4),
+                  mean_latency_s=round(st["mean_s"], 4), sims_per_s=round(st["sims_per_s"], 3),
+                  mlups=round(lu / st["span_s"] / 1e6, 1))
+    log("served p50 %.3f s p99 %.3f s, %.2f sims/s" % (st["p50_s"], st["p99_s"], st["sims_per_s"]))
+    return batched, served
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=6,
+                    help="oracle steps on the full grid for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary precisions and the cache-resident size")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--seg-rows", type=int, default=0,
+                    help="force the launch shape (rows per wave) instead of autotuning")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched and served runs")
+    ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--serve-requests", type=int, default=110)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the step runs on a single MI355X and this "
+              "build has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1803_01756_amd import configs, lbm
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    lbm.lib()
+
+    log("bandwidth probe (plain copy, 1 GiB)")
+    probe_gbs, _ = lbm.lbm_bandwidth_probe(1 << 30, 20)
+
+    p = configs.large_channel(lbm.LBM_FP32_DEV)
+    rho0 = configs.initial_density(p, seed=1)
+    n = fluid_nodes(p)
+    log("8192x512 fp32: tune + %d warmup + %d timed steps" % (args.warmup, args.steps))
+    ms, wall_ms, seg, waves, red = run_config(p, rho0, args.steps, args.warmup,
+                                              tune=not args.no_tune, seg_rows=args.seg_rows)
+    ms_step = ms / args.steps
+    mlups = n * args.steps / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_LUP[0] * n / (ms_step * 1e-3) / 1e9
+    traffic = counter_traffic()
+    log("fp32 %.4f ms/step  %.0f MLUPS  %.0f GB/s algorithmic" % (ms_step, mlups, achieved))
+
+    extra = {}
+    if not args.no_extra:
+        k = max(200, args.steps // 4)
+        for name, prec in (("fp64", lbm.LBM_FP64), ("fp32_massexact", lbm.LBM_FP32_DEV_MASSEXACT)):
+            q = configs.large_channel(prec)
+            log("8192x512 %s: %d steps" % (name, k))
+            m2, _, s2, _, _ = run_config(q, rho0, k, 20, tune=not args.no_tune)
+            extra[name] = dict(mlups=round(n * k / (m2 * 1e-3) / 1e6, 1),
+                               ms_per_step=round(m2 / k, 5), seg_rows=s2,
+                               hbm_gbs_algorithmic=round(BYTES_PER_LUP[prec] * n / (m2 / k * 1e-3) / 1e9, 1))
+        q = configs.single_gpu_channel(90.0, lbm.LBM_FP32_DEV)
+        r2 = configs.initial_density(q, seed=1)
+        log("2048x256 fp32 (cache-resident): %d steps" % (4 * k))
+        m3, _, s3, _, _ = run_config(q, r2, 4 * k, 50, tune=not args.no_tune)
+        n3 = fluid_nodes(q)
+        extra["2048x256_fp32"] = dict(mlups=round(n3 * 4 * k / (m3 * 1e-3) / 1e6, 1),
+                                      ms_per_step=round(m3 / (4 * k), 5), seg_rows=s3)
+
+    batched = served = None
+    if not args.no_batch:
+        batched, served = batch_and_serve(args)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle: %d steps on the full 8192x512 grid" % args.cpu_steps)
+        cm, dt = oracle_mlups(p, rho0, args.cpu_steps)
+        cpu = dict(value=round(cm, 3), unit="MLUPS", cores=1, kind="oracle",
+                   sample="FP64 oracle, single thread, %d steps of the full 8192x512 grid "
+                          "(%.1f s)" % (args.cpu_steps, dt))
+
+    line = {
+        "metric": "MLUPS (fused FP32 step, 8192x512 channel) & % HBM roofline",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plate channel 8192x512, FP32 deviation storage, Tw=0.78Tc, "
+                               "75 deg wall, drive 2e-6 / 4000 steps, seeded vapour noise",
+                   "Nx": p.Nx, "Ny": p.Ny, "fluid_nodes": n, "seg_rows": seg, "waves": waves},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "bytes_per_lup": BYTES_PER_LUP[0],
+                     "copy_probe_gbs": round(probe_gbs, 1),
+                     "frac_of_copy_probe": round(achieved / probe_gbs, 4)},
+        "cpu_baseline": cpu,
+        "wall_ms_timed": round(wall_ms, 3),
+        "mass": red[0],
+        "extra": extra,
+        "batched": batched,
+        "served": served,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,8 +82,9 @@ typedef struct {
     double T_0, T_w;        /* initial fluid and plate temperatures               */
     double g_osc, period;   /* drive amplitude and period in steps (<= 0: off)    */
     double g_x, g_y;        /* Eq. 15 gravity                                      */
-    double rho_v;           /* Eq. 15 reference vapour density; <= 0: Maxwell gas */
-    double rho_ref;         /* density of the stored deviations; <= 0: rho_v      */
+    double rho_v;           /* Eq. 15 reference vapour density; < 0: Maxwell gas  */
+    double rho_ref;         /* density of the stored deviations; <= 0: rho_v (or
+                               the Maxwell gas density when rho_v is 0)          */
     int32_t precision;      /* LBM_FP32_DEV, LBM_FP64 or LBM_FP32_DEV_MASSEXACT   */
     uint32_t flags;         /* LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y   */
 } lbm_params;
@@ -92,14 +93,16 @@ typedef struct {
  * omega = 0.344, T_c derived, G = -1, theta = 0.104, G_w = psi_w = 0,
  * s_rho = s_j = 1, s_e = s_zeta = 0.8, s_q = 1.1, tau_g = tau_l = 1,
  * C_v = 5, lambda = 0.25 (Sec. 3.2), T_0 = 0.86 T_c, T_w = 0.80 T_c,
- * g_osc = 1e-6, period = 2000, no gravity, FP32_DEV, no flags.  T_0, T_w
- * and the densities stay <= 0 ("derive") until lbm_params_resolve(). */
+ * g_osc = 1e-6, period = 2000, no gravity, FP32_DEV, no flags.  T_c, T_0,
+ * T_w, rho_g, rho_l, rho_ref stay 0 and rho_v -1 ("derive") until
+ * lbm_params_resolve(). */
 void lbm_params_default(lbm_params* p);
 
-/* Derive the fields left at <= 0: T_c (critical point of Eq. 11 with
- * phi = 1), T_0 = 0.86 T_c, T_w = 0.80 T_c, rho_g and rho_l (Maxwell
- * coexistence at T_0), rho_v = rho_g, rho_ref = rho_v.  LBM_EINVAL if T_0 is
- * not below T_c while a coexistence density is requested. */
+/* Derive the fields left at <= 0 (rho_v: < 0): T_c (critical point of
+ * Eq. 11 with phi = 1), T_0 = 0.86 T_c, T_w = 0.80 T_c, rho_g and rho_l
+ * (Maxwell coexistence at T_0), rho_v = rho_g, rho_ref = rho_v (rho_g when
+ * rho_v is 0).  LBM_EINVAL if T_0 is not below T_c while a coexistence
+ * density is requested. */
 lbm_status lbm_params_resolve(lbm_params* p);
 
 /* Critical point (rho_c, T_c) of the Peng-Robinson EOS of Eq. 11 and the
@@ -108,6 +111,11 @@ lbm_status lbm_params_resolve(lbm_params* p);
 lbm_status lbm_eos_critical(double a, double b, double R, double* rho_c, double* T_c);
 lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_g, double* rho_l,
                                double* p_sat);
+
+/* P_EOS(rho, T) of Eq. 11 and the pseudopotential psi of Eq. 10 (clamped at
+ * 0) for the EOS constants and G of *p (T_c <= 0: derived).  Host FP64; used
+ * e.g. to turn a virtual wall density into psi_w. */
+lbm_status lbm_eos_pressure(const lbm_params* p, double rho, double T, double* P, double* psi);
 
 /* Device bytes a simulation with these parameters needs (two population
  * buffers, two temperature buffers, moment scratch), for callers that
@@ -176,6 +184,75 @@ lbm_status lbm_get_launch(const lbm_sim* sim, int32_t* seg_rows, int32_t* waves)
  * restored around the trials) and keep the fastest.  best_ms receives the
  * best time per step (may be NULL). */
 lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_trial, double* best_ms);
+
+/* ---- batched and served runs: a pool of channel slots -------------------
+ *
+ * A pool steps many independent channels (each with its own grid and
+ * parameters, FP32 deviation storage) together: lbm_pool_run enqueues a
+ * chunk of steps as one batched launch per step over every active slot.
+ * Admission is by device footprint against the pool's byte cap; start-up and
+ * read-out run on a second stream, so slots can be admitted and results read
+ * while a chunk runs (continuous batching).  A slot's results are bitwise
+ * those of the same channel run alone with lbm_create/lbm_step. */
+
+/* Device bytes one slot with these parameters holds (two population
+ * buffers, two temperature planes); 0 if the parameters are invalid. */
+size_t lbm_pool_footprint(const lbm_params* p);
+
+/* Create an empty pool admitting up to cap_bytes of slot footprints;
+ * stream: hipStream_t for the batched chunks, NULL for a private one. */
+lbm_status lbm_pool_create(size_t cap_bytes, void* stream, lbm_pool** out);
+
+/* Admit a channel that is to run nsteps steps.  rho0: host Nx*Ny initial
+ * densities or NULL (uniform rho_v).  *slot receives its id.
+ * LBM_ENOMEM when its footprint does not fit under the cap (the caller keeps
+ * the request queued), LBM_EINVAL for invalid parameters or a precision
+ * other than LBM_FP32_DEV. */
+lbm_status lbm_pool_admit(lbm_pool* pool, const lbm_params* p, const double* rho0,
+                          int64_t nsteps, int32_t* slot);
+
+/* Enqueue chunk_steps steps (asynchronous) for every slot with steps left;
+ * a slot with fewer left takes only those. */
+lbm_status lbm_pool_run(lbm_pool* pool, int32_t chunk_steps);
+
+/* Block until at most max_pending enqueued chunks are still running (host
+ * back-pressure for a serving loop that enqueues ahead of the device). */
+lbm_status lbm_pool_wait(lbm_pool* pool, int32_t max_pending);
+
+/* Non-blocking: ids of slots that have finished all their steps and were
+ * not reported before (at most max of them) into done[], count in *ndone. */
+lbm_status lbm_pool_poll(lbm_pool* pool, int32_t* done, int32_t max, int32_t* ndone);
+
+/* rho, u, T of a slot at its current time level into host arrays of Nx*Ny
+ * doubles (any may be NULL), as lbm_moments.  Waits for that slot only. */
+lbm_status lbm_pool_moments(lbm_pool* pool, int32_t slot, double* rho, double* ux, double* uy,
+                            double* T);
+
+/* Retire a slot; its footprint returns to the cap and its id may be reused. */
+lbm_status lbm_pool_release(lbm_pool* pool, int32_t slot);
+
+/* Destroy the pool and every slot in it; NULL is accepted. */
+lbm_status lbm_pool_destroy(lbm_pool* pool);
+
+/* Active slots, bytes in use and the cap (any pointer may be NULL). */
+lbm_status lbm_pool_info(const lbm_pool* pool, int32_t* active, size_t* bytes_used,
+                         size_t* cap_bytes);
+
+/* Time level of a slot (after the work enqueued so far), -1 if no such slot. */
+int64_t lbm_pool_slot_time(const lbm_pool* pool, int32_t slot);
+
+/* Rows per wave of every slot's launch shape (<= 0: per-slot default). */
+lbm_status lbm_pool_set_launch(lbm_pool* pool, int32_t seg_rows);
+
+/* Wait for all work of the pool. */
+lbm_status lbm_pool_synchronize(lbm_pool* pool);
+
+/* Plain device-to-device copy of `bytes` (rounded down to a multiple of 16)
+ * repeated `iters` times on a private stream: achieved bandwidth counting
+ * read + write (2 * bytes per copy) in GB/s, and the time per copy.  The
+ * roofline denominator the step kernel is compared with, next to the vendor
+ * peak; it allocates and frees two buffers of `bytes`. */
+lbm_status lbm_bandwidth_probe(size_t bytes, int32_t iters, double* gbps, double* ms_per_copy);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,102 @@
+"""Contact angle versus wall potential, measured with the FP64 oracle.
+
+TEST INFRASTRUCTURE: runs only the oracle.  Writes
+tests/golden/contact_angle_table.json, the table that maps the virtual wall
+density fraction phi_w = (rho_w - rho_g) / (rho_l - rho_g) (G_w = G,
+psi_w = psi(rho_w, T_0), Eq. 14) to the static contact angle.
+
+Recipe: a 160 x 70 channel at 0.86 Tc with frozen temperature and no drive;
+a half-disc of liquid of radius 22 centred on the lower plate (a tanh
+profile of width 5 between the Maxwell densities); 12000 steps.  The
+interface is the rho = (rho_l + rho_g)/2 contour, located by linear
+interpolation along rows and columns; points more than 3 rows above the
+plate are fitted with a circle (algebraic least squares), and the angle
+follows from where that circle meets the wall plane y = 1/2:
+cos(theta) = (1/2 - y_c) / R.  A droplet whose lowest interface point lies
+more than 4 rows above the plate has left it and counts as 180 degrees.
+
+    python oracle/calibrate_contact_angle.py [fractions...]
+"""
+import json
+import os
+import sys
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+NX, NY, R0, STEPS = 160, 70, 22.0, 12000
+FRACTIONS = [0.15, 0.2, 0.25, 0.3, 0.35, 0.38, 0.41, 0.43, 0.45, 0.5, 0.55, 0.6, 0.65]
+
+
+def interface_points(rho, thr):
+    pts = []
+    ny, nx = rho.shape
+    for y in range(1, ny - 1):
+        row = rho[y]
+        for x in range(nx):
+            a, b = row[x], row[(x + 1) % nx]
+            if (a - thr) * (b - thr) < 0:
+                pts.append((x + (thr - a) / (b - a), float(y)))
+    for x in range(nx):
+        col = rho[:, x]
+        for y in range(1, ny - 2):
+            a, b = col[y], col[y + 1]
+            if (a - thr) * (b - thr) < 0:
+                pts.append((float(x), y + (thr - a) / (b - a)))
+    return np.array(pts)
+
+
+def circle_fit(pts):
+    x, y = pts[:, 0], pts[:, 1]
+    A = np.column_stack([x, y, np.ones_like(x)])
+    c, *_ = np.linalg.lstsq(A, x * x + y * y, rcond=None)
+    xc, yc = c[0] / 2, c[1] / 2
+    return xc, yc, np.sqrt(c[2] + xc * xc + yc * yc)
+
+
+def measure(frac):
+    from oracle import oracle as O
+    p = O.default_params(Nx=NX, Ny=NY, flags=O.FREEZE_T, period=0.0, g_osc=0.0)
+    g, l = p.rho_g, p.rho_l
+    p.Gw = p.G
+    p.psiw = O.psi(p, g + frac * (l - g), p.T0)
+    y, x = np.mgrid[0:NY, 0:NX].astype(float)
+    r = np.hypot(x - NX / 2, y - 0.5)
+    rho0 = 0.5 * (l + g) - 0.5 * (l - g) * np.tanh(2 * (r - R0) / 5.0)
+    s = O.Sim(p, rho0)
+    s.step(STEPS)
+    rho = s.moments()[0]
+    thr = 0.5 * (l + g)
+    pts = interface_points(rho, thr)
+    if len(pts) == 0:
+        return dict(frac=frac, psi_w=p.psiw, angle=0.0, note="no droplet left (film)")
+    if pts[:, 1].min() > 4.5:
+        return dict(frac=frac, psi_w=p.psiw, angle=180.0, note="droplet left the plate")
+    pts = pts[pts[:, 1] > 3.5]
+    xc, yc, R = circle_fit(pts)
+    ang = float(np.degrees(np.arccos(np.clip((0.5 - yc) / R, -1.0, 1.0))))
+    return dict(frac=frac, psi_w=p.psiw, angle=round(ang, 2), radius=round(float(R), 3),
+                centre_y=round(float(yc), 3))
+
+
+def main():
+    fr = [float(a) for a in sys.argv[1:]] or FRACTIONS
+    with ProcessPoolExecutor(max_workers=min(4, len(fr))) as ex:
+        rows = list(ex.map(measure, fr))
+    for r in rows:
+        print(json.dumps(r), flush=True)
+    out = dict(source="oracle/calibrate_contact_angle.py (FP64 oracle only)",
+               recipe=__doc__.split("Recipe: ")[1].split("\n\n")[0].replace("\n", " "),
+               T_over_Tc=0.86, G_w_equals_G=True, table=rows)
+    path = os.path.join(ROOT, "tests", "golden", "contact_angle_table.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm_hip.so")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["lbm_kernels.hip", "lbm_pool.hip", "lbm_runtime.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp", "lbm_pool.cpp"]
 
 
 def hipcc() -> str:
@@ -30,7 +30,10 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     tmp = LIB + ".tmp%d" % os.getpid()
+    # code object v5: accepted by the system ROCm runtime and by the one that
+    # PyTorch-ROCm ships
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-mcode-object-version=5",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] + srcs
     if verbose:

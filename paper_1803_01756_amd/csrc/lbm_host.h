@@ -1,0 +1,31 @@
+// Host helpers shared by the single-channel runtime and the slot pool.
+// Internal; not part of the C-ABI.
+#pragma once
+
+#include <cstddef>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace lbmhost {
+
+constexpr int kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Device memory layout of one channel: two population buffers
+// [9][rows][pitch], optional mass-exact low planes, two temperature planes,
+// then the moment arrays and reduction scratch.
+struct Layout {
+    int pitch, rows;
+    size_t plane, esz;
+    size_t off_f[2], off_lo[2], off_T[2], off_mom, off_scr, off_part, off_out, total;
+};
+
+lbm_status fail(lbm_status st, const char* fmt, ...);
+bool make_layout(const lbm_params& p, Layout* L);
+lbm_status validate(const lbm_params& p);
+int default_seg_rows(const lbm_params& p, int rows);
+void fill_grid(const lbm_params& p, const Layout& L, int seg_rows, lbmk::Grid& g);
+void fill_phys(const lbm_params& p, lbmk::Phys& k);
+
+}  // namespace lbmhost

@@ -16,6 +16,16 @@ constexpr int kLanes = 64;
 constexpr int kHalo = 5;
 constexpr int kOwned = kLanes - 2 * kHalo;
 
+// Constants that enter arithmetic done in the storage precision R, given in
+// R on the host so that the kernels never convert them per use.
+template <class R>
+struct PhysR {
+    R s_rho, s_e, s_z, s_j, s_q, c_e, c_z;
+    R b, rkA, rkB1, rkB2, inv_Cv, lambda;
+    R T_ref, dT_wall, rho_ref, rho_v, g_x, g_y;
+    R rho_g, inv_drho, tau_g, dtau;
+};
+
 // Uniform physical constants, resolved on the host in FP64.  The kernels
 // read them from the kernel-argument segment (scalar registers).
 struct Phys {
@@ -28,11 +38,13 @@ struct Phys {
     double s_rho, s_e, s_z, s_j, s_q;   // Eq. 3 rates
     double tau_g, dtau, rho_g, inv_drho;// Eq. 5 (inv_drho = 0: constant tau)
     double inv_Cv, lambda;              // Eq. 16
-    double drive;                       // g_osc sin(2 pi n / period) at this step
+    double g_osc, period;               // drive g_osc sin(2 pi n / period) along +x
     double g_x, g_y, rho_v;             // Eq. 15
     double rkA, rkB1, rkB2;             // R, a k (1+k)/sqrt(Tc), a k^2 / Tc
     uint32_t flags;                     // LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y
     uint32_t pad_;
+    PhysR<float> rf;                    // the same constants in FP32 and FP64
+    PhysR<double> rd;
 };
 
 struct Grid {
@@ -57,20 +69,41 @@ struct Bufs {
 
 constexpr int kWavesPerBlock = 4;
 
-// One fused time step (pull-stream + bounce-back, psi, forces, u, MRT
-// collision, RK4 temperature) over all units of the grid.
+// One fused time step n -> n+1 (pull-stream + bounce-back, psi, forces, u,
+// MRT collision, RK4 temperature) over all units of the grid.
 hipError_t launch_step_f32(const Grid& g, const Phys& k, const Bufs<float>& b, bool mass_exact,
+                           int64_t n, hipStream_t s);
+hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, int64_t n,
                            hipStream_t s);
-hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, hipStream_t s);
+
+// One channel of a batch (FP32 deviation storage).  The table of slots is
+// constant during a chunk of steps; step i of the chunk reads buffer
+// (cur + i) & 1 and writes the other, at time level n0 + i, and a slot takes
+// part only while i < steps_left.
+struct Slot {
+    Grid g;
+    Phys k;
+    float* f[2];
+    float* T[2];
+    int64_t n0;
+    int cur_f, cur_T;
+    int steps_left;
+    int unit_begin;  // first unit of this slot in the batch numbering
+};
+
+// Step i of a chunk over every slot of the table (slots sorted by
+// unit_begin, total_units = sum of their units).
+hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, int step_i,
+                               hipStream_t s);
 
 // rho, u (half force) and T at the current time level into device arrays of
 // Nx*Ny doubles; scratch holds 3*Nx*Ny doubles.
 hipError_t launch_moments_f32(const Grid& g, const Phys& k, const float* f, const float* f0lo,
                               const float* T, double* scratch, double* rho, double* ux,
-                              double* uy, double* Tout, hipStream_t s);
+                              double* uy, double* Tout, int64_t n, hipStream_t s);
 hipError_t launch_moments_f64(const Grid& g, const Phys& k, const double* f, const double* T,
                               double* scratch, double* rho, double* ux, double* uy,
-                              double* Tout, hipStream_t s);
+                              double* Tout, int64_t n, hipStream_t s);
 
 // Rest-equilibrium start from a device density field rho0 (Nx*Ny doubles).
 hipError_t launch_init_f32(const Grid& g, const Phys& k, const double* rho0, float* f,
@@ -85,5 +118,8 @@ constexpr int kReduceBlocks = 256;
 hipError_t launch_reduce(const double* rho, const double* ux, const double* uy,
                          const double* T, int n, double Cv, double* partials, double* out,
                          hipStream_t s);
+
+// Plain device copy of bytes (a multiple of 16) for the bandwidth probe.
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace lbmk

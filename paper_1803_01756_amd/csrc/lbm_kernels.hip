@@ -32,12 +32,12 @@ constexpr uint32_t kFreezeT = 1u, kSinglePhase = 2u;
 
 // ---- lane shifts (DPP wave_shr:1 / wave_shl:1) ---------------------------
 // at_xm(v): the value lane l-1 holds (column x-1); at_xp: lane l+1 (x+1).  The
-// edge lanes keep their own value; they lie in the halo.
+// edge lanes (which lie in the halo) read 0.
 __device__ __forceinline__ int dpp_shr1(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int dpp_shl1(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);
 }
 __device__ __forceinline__ float at_xm(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
 __device__ __forceinline__ float at_xp(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
@@ -73,6 +73,31 @@ __device__ __forceinline__ Tri<R> tri_const(R v) {
     t.m = v;
     t.p = v;
     return t;
+}
+
+// ---- raw buffer access ------------------------------------------------------
+// The planes are addressed through buffer resources: a wave-uniform byte
+// offset (plane and row, scalar register) plus a per-lane byte offset (the
+// column), so a load or store needs no per-lane 64-bit address arithmetic.
+// num_records is the buffer size, so an access outside it reads 0 / is
+// dropped by the hardware range check.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufWord3 = 0x00020000;  // gfx9 raw-buffer format word
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kBufWord3);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
 }
 
 // ---- rows -----------------------------------------------------------------
@@ -138,22 +163,96 @@ __device__ __forceinline__ void pull_row(const S* __restrict__ f, const Grid& g,
     d[8] = f[o8];
 }
 
+// The same pull through buffer resources.  Byte offsets: vx, vm, vp are the
+// lane's columns x, x-1, x+1 times sizeof(S); planes and rows are uniform.
+template <class S>
+__device__ __forceinline__ void pull_row_buf(__amdgpu_buffer_rsrc_t f, const Grid& g,
+                                             const RowK& r, unsigned vx, unsigned vm,
+                                             unsigned vp, S d[9]) {
+    const unsigned P = g.plane * (unsigned)sizeof(S), pitch = (unsigned)g.pitch * sizeof(S);
+    const unsigned rc = (unsigned)r.sr * pitch;
+    unsigned rdn, rup;
+    if (g.periodic_y) {
+        int a = r.sr - 1, b = r.sr + 1;
+        if (a < 0) a += g.rows;
+        if (b >= g.rows) b -= g.rows;
+        rdn = (unsigned)a * pitch;
+        rup = (unsigned)b * pitch;
+    } else {
+        rdn = rc - pitch;
+        rup = rc + pitch;
+    }
+    const S t = S(0);
+    d[0] = bload(f, vx, rc, t);
+    d[1] = bload(f, vm, P + rc, t);
+    d[3] = bload(f, vp, 3 * P + rc, t);
+    if (r.bb_lo) {
+        d[2] = bload(f, vx, 4 * P + rc, t);
+        d[5] = bload(f, vx, 7 * P + rc, t);
+        d[6] = bload(f, vx, 8 * P + rc, t);
+    } else {
+        d[2] = bload(f, vx, 2 * P + rdn, t);
+        d[5] = bload(f, vm, 5 * P + rdn, t);
+        d[6] = bload(f, vp, 6 * P + rdn, t);
+    }
+    if (r.bb_hi) {
+        d[4] = bload(f, vx, 2 * P + rc, t);
+        d[7] = bload(f, vx, 5 * P + rc, t);
+        d[8] = bload(f, vx, 6 * P + rc, t);
+    } else {
+        d[4] = bload(f, vx, 4 * P + rup, t);
+        d[7] = bload(f, vp, 7 * P + rup, t);
+        d[8] = bload(f, vm, 8 * P + rup, t);
+    }
+}
+
+// ---- arithmetic helpers -------------------------------------------------------
+// FP32: the hardware reciprocal and square root (about 1 ulp) replace the
+// IEEE division / correctly rounded square root sequences.  FP64 (the FP64
+// storage build) keeps IEEE division and sqrt.
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+
+// FP64 reciprocal and square root from the FP32 hardware estimates refined by
+// Newton steps (two for 1/x, two for 1/sqrt(x)): relative error near 1 ulp of
+// FP64 for the positive, normal arguments used here.
+__device__ __forceinline__ double rcp_d(double x) {
+    double y = (double)__builtin_amdgcn_rcpf((float)x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double sqrt_d(double x) {
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    const double h = 0.5 * x;
+    y = y * fma(-h, y * y, 1.5);
+    y = y * fma(-h, y * y, 1.5);
+    return x * y;
+}
+
 // Eqs. 10-11: psi = sqrt(2 (P_EOS(rho, T) - rho/3) / G), clamped at 0.
 // FP64 throughout: the Shan-Chen force is a difference of neighbouring psi
 // values and the FP32 rounding of psi itself would be of the order of that
-// difference in a nearly uniform vapour.
-template <bool kSqrtPhiF32>
+// difference in a nearly uniform vapour.  With s = 1 + k (1 - sqrt(T/Tc)),
+// D = 1 + 2 b rho - b^2 rho^2:
+//   P = [rho R T D - a s^2 rho^2 (1 - b rho)] / ((1 - b rho) D).
+// kF32: sqrt(T/Tc) in FP32 (its rounding enters phi as a smooth relative
+// error, not a neighbour difference); the FP64 build takes it in FP64.
+template <bool kF32>
 __device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k) {
-    double st;
-    if (kSqrtPhiF32)
-        st = (double)__builtin_sqrtf((float)(T * k.inv_Tc));
-    else
-        st = sqrt(T * k.inv_Tc);
+    const double st = kF32 ? (double)__builtin_amdgcn_sqrtf((float)(T * k.inv_Tc))
+                           : sqrt_d(T * k.inv_Tc);
     const double s = 1.0 + k.kappa * (1.0 - st);
     const double br = k.b * rho;
-    const double P = rho * k.R * T / (1.0 - br) - k.a * (s * s) * rho * rho / (1.0 + br * (2.0 - br));
+    const double omb = 1.0 - br;
+    const double D = 1.0 + br * (2.0 - br);
+    const double num = rho * (k.R * T * D - k.a * (s * s) * rho * omb);
+    const double P = num * rcp_d(omb * D);
     const double arg = 2.0 * (P - rho * (1.0 / 3.0)) * k.inv_G;
-    return arg > 0.0 ? sqrt(arg) : 0.0;
+    return arg > 0.0 ? sqrt_d(arg) : 0.0;
 }
 
 // Eq. 9 + Eq. 14 in one sum: the solid rows carry the effective potential
@@ -176,12 +275,20 @@ __device__ __forceinline__ double wall_adhesion_y(const RowK& r, double psi_c, c
     return f;
 }
 
+template <class R>
+__device__ __forceinline__ const PhysR<R>& pr(const Phys& k);
+template <>
+__device__ __forceinline__ const PhysR<float>& pr<float>(const Phys& k) { return k.rf; }
+template <>
+__device__ __forceinline__ const PhysR<double>& pr<double>(const Phys& k) { return k.rd; }
+
 // MRT collision, Eqs. 6-8, in deviation moments: m'_k = m_k - rho_ref (M w)_k.
 // Returns the post-collision deviations in d (overwritten).
 template <class R>
 __device__ __forceinline__ void collide(R d[9], R drho, R rho, R ux, R uy, R Fx, R Fy, R th,
                                         R sv, const Phys& k) {
-    const R s_rho = (R)k.s_rho, s_e = (R)k.s_e, s_z = (R)k.s_z, s_j = (R)k.s_j, s_q = (R)k.s_q;
+    const PhysR<R>& c = pr<R>(k);
+    const R s_rho = c.s_rho, s_e = c.s_e, s_z = c.s_z, s_j = c.s_j, s_q = c.s_q;
     const R axis = (d[1] + d[2]) + (d[3] + d[4]);
     const R diag = (d[5] + d[6]) + (d[7] + d[8]);
     R m[9];
@@ -195,7 +302,7 @@ __device__ __forceinline__ void collide(R d[9], R drho, R rho, R ux, R uy, R Fx,
     m[7] = (d[1] + d[3]) - (d[2] + d[4]);
     m[8] = (d[5] + d[7]) - (d[6] + d[8]);
     const R jx = rho * ux, jy = rho * uy;
-    const R rinv = (R)1 / rho;
+    const R rinv = rcp_r(rho);
     const R j2r = (jx * jx + jy * jy) * rinv;
     R meq[9];
     meq[0] = drho;
@@ -210,8 +317,8 @@ __device__ __forceinline__ void collide(R d[9], R drho, R rho, R ux, R uy, R Fx,
     const R uF = ux * Fx + uy * Fy;
     R S[9];
     S[0] = (R)0;
-    S[1] = (R)6 * uF + (R)k.c_e * th;
-    S[2] = (R)-6 * uF - (R)k.c_z * th;
+    S[1] = (R)6 * uF + c.c_e * th;
+    S[2] = (R)-6 * uF - c.c_z * th;
     S[3] = Fx;
     S[4] = -Fx;
     S[5] = Fy;
@@ -251,25 +358,22 @@ struct Coef {
 };
 template <class R>
 __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, const Phys& k) {
-    const R br = (R)k.b * rho;
-    const R Dinv = (R)1 / ((R)1 + br * ((R)2 - br));
-    const R A = rho * (R)k.rkA / ((R)1 - br);
-    const R r2D = rho * rho * Dinv;
-    const R c = (R)k.inv_Cv / rho;
+    const PhysR<R>& pc = pr<R>(k);
+    const R br = pc.b * rho;
+    const R omb = (R)1 - br;
+    const R D = (R)1 + br * ((R)2 - br);
+    const R inv = rcp_r(omb * D * rho);  // 1 / ((1 - b rho) D rho)
+    const R A = rho * rho * pc.rkA * D * inv;
+    const R r2D = rho * rho * rho * omb * inv;
+    const R c = pc.inv_Cv * omb * D * inv;
     Coef<R> q;
     q.ux = ux;
     q.uy = uy;
-    q.q1 = c * divu * (A - (R)k.rkB2 * r2D);
-    q.q2 = c * divu * (R)k.rkB1 * r2D;
-    q.q3 = c * (R)k.lambda;
+    q.q1 = c * divu * (A - pc.rkB2 * r2D);
+    q.q2 = c * divu * pc.rkB1 * r2D;
+    q.q3 = c * pc.lambda;
     return q;
 }
-template <class R>
-__device__ __forceinline__ R sqrt_r(R v);
-template <>
-__device__ __forceinline__ float sqrt_r<float>(float v) { return __builtin_sqrtf(v); }
-template <>
-__device__ __forceinline__ double sqrt_r<double>(double v) { return sqrt(v); }
 
 // K(T) on the stage field (deviations tS, tC, tN of rows y-1, y, y+1).
 template <class R>
@@ -305,6 +409,13 @@ struct RealOf<double> {
     using T = double;
 };
 
+// Oscillating drive at time level n, evaluated on the device so that a channel
+// run alone and inside a batch sees the same bits.
+__device__ __forceinline__ double drive_at(const Phys& k, long long n) {
+    return k.period > 0.0 ? k.g_osc * sin(2.0 * 3.14159265358979323846 * (double)n / k.period)
+                          : 0.0;
+}
+
 // XCD-aware unit index: blocks are dispatched round-robin over the eight
 // XCDs, so consecutive units (neighbouring strips, which share halo columns)
 // are mapped to blocks that land on the same XCD and its L2.
@@ -314,13 +425,12 @@ __device__ __forceinline__ int unit_of_block(int nblocks_pad) {
     return ((b & 7) * per + (b >> 3));
 }
 
+// One wave's share of a step: the strip and row segment of `unit`.
 template <class S, bool kMX>
-__global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Phys k, Bufs<S> B) {
+__device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bufs<S>& B,
+                                          double drive, int unit) {
     using R = typename RealOf<S>::T;
-    constexpr bool kF32 = sizeof(S) == 4;
     const int lane = threadIdx.x & (kLanes - 1);
-    const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + (threadIdx.x >> 6);
-    if (unit >= g.n_units) return;  // whole waves only
     const int strip = unit % g.n_strips;
     const int seg = unit / g.n_strips;
 
@@ -339,9 +449,11 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
 
     const bool freezeT = (k.flags & kFreezeT) != 0;
     const bool single = (k.flags & kSinglePhase) != 0;
-    const R T_ref = (R)k.T_ref;
-    const R dTw = (R)k.dT_wall;
-    const R rho_ref = (R)k.rho_ref;
+    const PhysR<R>& kr_ = pr<R>(k);
+    const R T_ref = kr_.T_ref;
+    const R dTw = kr_.dT_wall;
+    const R rho_ref = kr_.rho_ref;
+    const R drive_r = (R)drive;
 
     // ---- register row windows ----
     // pulled deviations and derived values of rows k (cur) and k-1 (prv)
@@ -355,11 +467,12 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
     R tn4 = 0, tn5 = 0;
     // velocity rows k-1, k-2, k-3
     Tri<R> ux1, ux2, ux3, uy1, uy2, uy3;
-    // heat coefficients rows k-2 .. k-5
-    Coef<R> cf2, cf3, cf4, cf5;
+    // heat coefficients rows k-2 .. k-5 (cf6, cf7 only pad the window to six
+    // rows, so that it returns to its registers after one six-row trip)
+    Coef<R> cf2, cf3, cf4, cf5, cf6, cf7;
     // RK stage fields: T1 rows k-2..k-4, T2 rows k-3..k-5, T3 rows k-4..k-6
     Tri<R> t1a, t1b, t1c, t2a, t2b, t2c, t3a, t3b, t3c;
-    R acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0;  // accumulated h's, rows k-2..k-5
+    R acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0, acc6 = 0, acc7 = 0;  // sum of h's, rows k-2..k-5
     double drdCur = 0.0, drdPrv = 0.0;         // mass-exact: FP64 deviation density
 
 #pragma unroll
@@ -367,23 +480,36 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
     psi0 = psi1 = psi2 = tri_const<double>(0.0);
     tn0 = tn1 = tn2 = tn3 = tri_const<R>(dTw);
     ux1 = ux2 = ux3 = uy1 = uy2 = uy3 = tri_const<R>(0);
-    cf2 = cf3 = cf4 = cf5 = Coef<R>{0, 0, 0, 0, 0};
+    cf2 = cf3 = cf4 = cf5 = cf6 = cf7 = Coef<R>{0, 0, 0, 0, 0};
     t1a = t1b = t1c = t2a = t2b = t2c = t3a = t3b = t3c = tri_const<R>(dTw);
 
-    const S* __restrict__ fin = B.fin;
-    const S* __restrict__ Tin = B.Tin;
+    const unsigned esz = (unsigned)sizeof(S);
+    const unsigned fbytes = 9u * g.plane * esz, tbytes = g.plane * esz;
+    const __amdgpu_buffer_rsrc_t rf_in = make_rsrc(B.fin, fbytes);
+    const __amdgpu_buffer_rsrc_t rf_out = make_rsrc(B.fout, fbytes);
+    const __amdgpu_buffer_rsrc_t rT_in = make_rsrc(B.Tin, tbytes);
+    const __amdgpu_buffer_rsrc_t rT_out = make_rsrc(B.Tout, B.Tout ? tbytes : 0u);
+    const __amdgpu_buffer_rsrc_t rlo_in = make_rsrc(B.f0lo_in, kMX ? g.plane * 4u : 0u);
+    const __amdgpu_buffer_rsrc_t rlo_out = make_rsrc(B.f0lo_out, kMX ? g.plane * 4u : 0u);
+    const unsigned vx = x * esz, vm = xm * esz, vp = xp * esz;
+    const unsigned rowb = (unsigned)g.pitch * esz;
 
-    for (int kr = ya - kHalo; kr < yb + kHalo; ++kr) {
+    // One row iteration; the loop below calls it six times per trip so that
+    // the row windows (depths 2, 3 and 6) rotate by renaming registers instead
+    // of moving them (a loop holding DPP operations is not unrolled by the
+    // compiler).  Padding iterations past the segment only read valid rows and
+    // store nothing; launch shapes with seg_rows + 10 a multiple of 6 need none.
+    auto row_iteration = [&](const int kr) {
         // ------------- stage A: pull row kr, rho, j, psi ------------------
         const RowK rA = row_info(kr, g);
         Tri<double> psiA;
         R dTA;
         if (rA.fluid) {
             S raw[9];
-            pull_row<S>(fin, g, rA, x, xm, xp, raw);
-            const S rawT = Tin[(unsigned)rA.sr * (unsigned)g.pitch + x];
+            pull_row_buf<S>(rf_in, g, rA, vx, vm, vp, raw);
+            const S rawT = bload(rT_in, vx, (unsigned)rA.sr * rowb, S(0));
             R lo = 0;
-            if (kMX) lo = (R)B.f0lo_in[(unsigned)rA.sr * (unsigned)g.pitch + x];
+            if (kMX) lo = (R)bload(rlo_in, x * 4u, (unsigned)rA.sr * (unsigned)g.pitch * 4u, 0.0f);
 #pragma unroll
             for (int q = 0; q < 9; ++q) dCur[q] = (R)raw[q];
             double drd;
@@ -404,7 +530,7 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
             rhoCur = (R)rho_d;
             dTA = (R)rawT;
             const double Td = k.T_ref + (double)dTA;
-            psiA = tri<double>(psi_eos<kF32>(rho_d, Td, k));
+            psiA = tri<double>(psi_eos<sizeof(S) == 4>(rho_d, Td, k));
         } else {
             drCur = 0;
             drdCur = 0.0;
@@ -429,9 +555,9 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
                 Fyd = wall_adhesion_y(rB, psi1.c, k);
             }
             const R rho = rhoPrv;
-            R Fx = (R)Fxd + rho * (R)k.drive + (rho - (R)k.rho_v) * (R)k.g_x;
-            R Fy = (R)Fyd + (rho - (R)k.rho_v) * (R)k.g_y;
-            const R rinv = (R)1 / rho;
+            R Fx = (R)Fxd + rho * drive_r + (rho - kr_.rho_v) * kr_.g_x;
+            R Fy = (R)Fyd + (rho - kr_.rho_v) * kr_.g_y;
+            const R rinv = rcp_r(rho);
             const R ux = (jxPrv + (R)0.5 * Fx) * rinv;
             const R uy = (jyPrv + (R)0.5 * Fy) * rinv;
             uxB = tri<R>(ux);
@@ -439,18 +565,19 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
             if (kr - 1 >= ya && kr - 1 < yb) {
                 // Eq. 8 theta term uses |F_m|^2 / psi^2 of the fluid-fluid force
                 R th = 0;
-                if (!single && psi1.c > 0.0) th = (R)((Fmx * Fmx + Fmy * Fmy) / (psi1.c * psi1.c));
+                if (!single && psi1.c > 0.0)
+                    th = (R)((Fmx * Fmx + Fmy * Fmy) * rcp_d(psi1.c * psi1.c));
                 // Eq. 5 with a clamped fraction
-                R fr = (rho - (R)k.rho_g) * (R)k.inv_drho;
+                R fr = (rho - kr_.rho_g) * kr_.inv_drho;
                 fr = fr < (R)0 ? (R)0 : (fr > (R)1 ? (R)1 : fr);
-                const R sv = (R)1 / ((R)k.tau_g + fr * (R)k.dtau);
+                const R sv = rcp_r(kr_.tau_g + fr * kr_.dtau);
                 R dn[9];
 #pragma unroll
                 for (int q = 0; q < 9; ++q) dn[q] = dPrv[q];
                 collide<R>(dn, drPrv, rho, ux, uy, Fx, Fy, th, sv, k);
                 if (own_lane) {
-                    const unsigned o = (unsigned)rB.sr * (unsigned)g.pitch + x;
-                    S* __restrict__ fo = B.fout;
+                    const unsigned so = (unsigned)rB.sr * rowb;
+                    const unsigned P = g.plane * esz;
                     if (kMX) {
                         // rest population takes whatever keeps sum_i d_i equal to
                         // the pre-collision deviation density (FP64), as (hi, lo)
@@ -458,13 +585,14 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
 #pragma unroll
                         for (int q = 1; q < 9; ++q) rest -= (double)(S)dn[q];
                         const float hi = (float)rest;
-                        fo[o] = (S)hi;
-                        B.f0lo_out[o] = (float)(rest - (double)hi);
+                        bstore((S)hi, rf_out, vx, so);
+                        bstore((float)(rest - (double)hi), rlo_out, x * 4u,
+                               (unsigned)rB.sr * (unsigned)g.pitch * 4u);
                     } else {
-                        fo[o] = (S)dn[0];
+                        bstore((S)dn[0], rf_out, vx, so);
                     }
 #pragma unroll
-                    for (int q = 1; q < 9; ++q) fo[q * g.plane + o] = (S)dn[q];
+                    for (int q = 1; q < 9; ++q) bstore((S)dn[q], rf_out, vx, q * P + so);
                 }
             }
         } else {
@@ -516,7 +644,7 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
             if (rF.fluid && kr - 5 >= ya && kr - 5 < yb) {
                 const R h4 = heat_rhs<R>(t3c, t3b, t3a, cf5, T_ref);
                 const R tnew = tn5 + (acc5 + h4) * ((R)1 / 6);
-                if (own_lane) B.Tout[(unsigned)rF.sr * (unsigned)g.pitch + x] = (S)tnew;
+                if (own_lane) bstore((S)tnew, rT_out, vx, (unsigned)rF.sr * rowb);
             }
         }
 
@@ -532,9 +660,13 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
         ux2 = ux1;
         uy3 = uy2;
         uy2 = uy1;
+        cf7 = cf6;
+        cf6 = cf5;
         cf5 = cf4;
         cf4 = cf3;
         cf3 = cf2;
+        acc7 = acc6;
+        acc6 = acc5;
         acc5 = acc4;
         acc4 = acc3;
         acc3 = acc2;
@@ -552,7 +684,63 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
         drdPrv = drdCur;
 #pragma unroll
         for (int q = 0; q < 9; ++q) dPrv[q] = dCur[q];
+    };
+    const int kr_end = yb + kHalo;
+    for (int kr = ya - kHalo; kr < kr_end; kr += 6) {
+        row_iteration(kr);
+        row_iteration(kr + 1);
+        row_iteration(kr + 2);
+        row_iteration(kr + 3);
+        row_iteration(kr + 4);
+        row_iteration(kr + 5);
     }
+}
+
+// wave index inside the block, as a wave-uniform value
+__device__ __forceinline__ int wave_in_block() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+template <class S, bool kMX>
+__global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Phys k, Bufs<S> B,
+                                                                     long long n) {
+    const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
+    if (unit >= g.n_units) return;  // whole waves only
+    step_unit<S, kMX>(g, k, B, drive_at(k, n), unit);
+}
+
+// Step i of a chunk over a batch of channels.  The slot of a unit is found by
+// a binary search over the slots' first units (wave-uniform).
+__global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_batched_kernel(
+    const Slot* __restrict__ slots, int n_slots, int total_units, int nblocks_pad, int step_i) {
+    const int unit = unit_of_block(nblocks_pad) * kWavesPerBlock + wave_in_block();
+    if (unit >= total_units) return;
+    int lo = 0, hi = n_slots - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (slots[mid].unit_begin <= unit) lo = mid; else hi = mid - 1;
+    }
+    const Slot& sl = slots[lo];
+    if (step_i >= sl.steps_left) return;
+    // local copies: the buffer stores of the step may alias the table as far
+    // as the compiler can tell, which would force reloads inside the loop
+    const Grid g = sl.g;
+    const Phys k = sl.k;
+    Bufs<float> B;
+    const int a = (sl.cur_f + step_i) & 1;
+    B.fin = a ? sl.f[1] : sl.f[0];
+    B.fout = a ? sl.f[0] : sl.f[1];
+    B.f0lo_in = nullptr;
+    B.f0lo_out = nullptr;
+    if (sl.k.flags & kFreezeT) {
+        B.Tin = sl.cur_T ? sl.T[1] : sl.T[0];
+        B.Tout = nullptr;
+    } else {
+        const int t = (sl.cur_T + step_i) & 1;
+        B.Tin = t ? sl.T[1] : sl.T[0];
+        B.Tout = t ? sl.T[0] : sl.T[1];
+    }
+    step_unit<float, false>(g, k, B, drive_at(k, sl.n0 + step_i), unit - sl.unit_begin);
 }
 
 // ---- moments: two passes over all nodes ------------------------------------
@@ -564,7 +752,6 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
                                                      double* __restrict__ scratch,
                                                      double* __restrict__ rho_out,
                                                      double* __restrict__ T_out) {
-    constexpr bool kF32 = sizeof(S) == 4;
     const int n = g.Nx * g.Ny;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -593,7 +780,7 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
     const double Td = k.T_ref + (double)T[(unsigned)r.sr * (unsigned)g.pitch + x];
     rho_out[i] = rho;
     T_out[i] = Td;
-    psi[i] = psi_eos<kF32>(rho, Td, k);
+    psi[i] = psi_eos<sizeof(S) == 4>(rho, Td, k);
     jx[i] = ((double)d[1] - (double)d[3]) + ((double)d[5] - (double)d[6]) +
             ((double)d[8] - (double)d[7]);
     jy[i] = ((double)d[2] - (double)d[4]) + ((double)d[5] + (double)d[6]) -
@@ -604,7 +791,7 @@ __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
                                                      const double* __restrict__ scratch,
                                                      const double* __restrict__ rho_in,
                                                      double* __restrict__ ux_out,
-                                                     double* __restrict__ uy_out) {
+                                                     double* __restrict__ uy_out, long long n_t) {
     const int n = g.Nx * g.Ny;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -640,7 +827,7 @@ __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
     else
         Fy = wall_adhesion_y(r, pC.c, k);
     const double rho = rho_in[i];
-    Fx += rho * k.drive + (rho - k.rho_v) * k.g_x;
+    Fx += rho * drive_at(k, n_t) + (rho - k.rho_v) * k.g_x;
     Fy += (rho - k.rho_v) * k.g_y;
     ux_out[i] = (jx[i] + 0.5 * Fx) / rho;
     uy_out[i] = (jy[i] + 0.5 * Fy) / rho;
@@ -736,46 +923,75 @@ __global__ __launch_bounds__(64) void reduce_pass2(const double* __restrict__ pa
 
 inline int blocks_for(int n, int bs) { return (n + bs - 1) / bs; }
 
+// ---- plain copy for the bandwidth probe (16-byte vectors, grid-stride) ----
+__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
+                                                   float4* __restrict__ dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 }  // namespace
 
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    hipLaunchKernelGGL(copy_kernel, dim3(256 * 32), dim3(256), 0, s,
+                       static_cast<const float4*>(src), static_cast<float4*>(dst), n);
+    return hipGetLastError();
+}
+
 template <class S, bool kMX>
-static hipError_t step_impl(const Grid& g, const Phys& k, const Bufs<S>& b, hipStream_t s) {
+static hipError_t step_impl(const Grid& g, const Phys& k, const Bufs<S>& b, int64_t n,
+                            hipStream_t s) {
     if (g.n_units <= 0) return hipSuccess;
     hipLaunchKernelGGL((step_kernel<S, kMX>), dim3(g.n_blocks_pad), dim3(kLanes * kWavesPerBlock),
-                       0, s, g, k, b);
+                       0, s, g, k, b, (long long)n);
     return hipGetLastError();
 }
 
 hipError_t launch_step_f32(const Grid& g, const Phys& k, const Bufs<float>& b, bool mass_exact,
-                           hipStream_t s) {
-    return mass_exact ? step_impl<float, true>(g, k, b, s) : step_impl<float, false>(g, k, b, s);
+                           int64_t n, hipStream_t s) {
+    return mass_exact ? step_impl<float, true>(g, k, b, n, s)
+                      : step_impl<float, false>(g, k, b, n, s);
 }
-hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, hipStream_t s) {
-    return step_impl<double, false>(g, k, b, s);
+hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, int64_t n,
+                           hipStream_t s) {
+    return step_impl<double, false>(g, k, b, n, s);
+}
+
+hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, int step_i,
+                               hipStream_t s) {
+    if (total_units <= 0 || n_slots <= 0) return hipSuccess;
+    const int nb = (total_units + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int nbp = (nb + 7) / 8 * 8;
+    hipLaunchKernelGGL(step_batched_kernel, dim3(nbp), dim3(kLanes * kWavesPerBlock), 0, s, slots,
+                       n_slots, total_units, nbp, step_i);
+    return hipGetLastError();
 }
 
 template <class S, bool kMX>
 static hipError_t moments_impl(const Grid& g, const Phys& k, const S* f, const float* f0lo,
                                const S* T, double* scratch, double* rho, double* ux, double* uy,
-                               double* Tout, hipStream_t s) {
+                               double* Tout, int64_t n_t, hipStream_t s) {
     const int n = g.Nx * g.Ny;
     hipLaunchKernelGGL((moments_pass1<S, kMX>), dim3(blocks_for(n, 256)), dim3(256), 0, s, g, k,
                        f, f0lo, T, scratch, rho, Tout);
     hipLaunchKernelGGL(moments_pass2, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, k,
-                       (const double*)scratch, (const double*)rho, ux, uy);
+                       (const double*)scratch, (const double*)rho, ux, uy, (long long)n_t);
     return hipGetLastError();
 }
 
 hipError_t launch_moments_f32(const Grid& g, const Phys& k, const float* f, const float* f0lo,
                               const float* T, double* scratch, double* rho, double* ux,
-                              double* uy, double* Tout, hipStream_t s) {
-    if (f0lo) return moments_impl<float, true>(g, k, f, f0lo, T, scratch, rho, ux, uy, Tout, s);
-    return moments_impl<float, false>(g, k, f, nullptr, T, scratch, rho, ux, uy, Tout, s);
+                              double* uy, double* Tout, int64_t n, hipStream_t s) {
+    if (f0lo)
+        return moments_impl<float, true>(g, k, f, f0lo, T, scratch, rho, ux, uy, Tout, n, s);
+    return moments_impl<float, false>(g, k, f, nullptr, T, scratch, rho, ux, uy, Tout, n, s);
 }
 hipError_t launch_moments_f64(const Grid& g, const Phys& k, const double* f, const double* T,
                               double* scratch, double* rho, double* ux, double* uy,
-                              double* Tout, hipStream_t s) {
-    return moments_impl<double, false>(g, k, f, nullptr, T, scratch, rho, ux, uy, Tout, s);
+                              double* Tout, int64_t n, hipStream_t s) {
+    return moments_impl<double, false>(g, k, f, nullptr, T, scratch, rho, ux, uy, Tout, n, s);
 }
 
 hipError_t launch_init_f32(const Grid& g, const Phys& k, const double* rho0, float* f,

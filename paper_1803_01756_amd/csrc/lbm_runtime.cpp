@@ -9,17 +9,23 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_host.h"
 #include "lbm_internal.h"
 
 using lbmk::Grid;
 using lbmk::Phys;
+using lbmhost::Layout;
+using lbmhost::fail;
 
 namespace {
-
 thread_local char g_err[512] = "no error";
+}
+
+namespace lbmhost {
 
 lbm_status fail(lbm_status st, const char* fmt, ...) {
     va_list ap;
@@ -28,6 +34,10 @@ lbm_status fail(lbm_status st, const char* fmt, ...) {
     va_end(ap);
     return st;
 }
+
+}  // namespace lbmhost
+
+namespace {
 
 #define HIPCHK(expr)                                                                      \
     do {                                                                                  \
@@ -126,14 +136,9 @@ bool coexistence(const Eos& E, double T, double* rg, double* rl, double* ps) {
     return true;
 }
 
-constexpr int kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+}  // namespace
 
-struct Layout {
-    int pitch, rows;
-    size_t plane, esz;
-    size_t off_f[2], off_lo[2], off_T[2], off_mom, off_scr, off_part, off_out, total;
-};
+namespace lbmhost {
 
 bool make_layout(const lbm_params& p, Layout* L) {
     const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
@@ -191,7 +196,12 @@ lbm_status validate(const lbm_params& p) {
     return LBM_OK;
 }
 
-}  // namespace
+}  // namespace lbmhost
+
+using lbmhost::align_up;
+using lbmhost::kAlign;
+using lbmhost::make_layout;
+using lbmhost::validate;
 
 struct lbm_sim {
     lbm_params p;
@@ -223,7 +233,7 @@ struct lbm_sim {
     double* out() const { return reinterpret_cast<double*>(base + L.off_out); }
 };
 
-namespace {
+namespace lbmhost {
 
 // default launch shape: enough waves to give each of the 1024 SIMDs about two
 // (the register budget of the fused kernel allows two resident per SIMD), but
@@ -237,28 +247,23 @@ int default_seg_rows(const lbm_params& p, int rows) {
     return sr;
 }
 
-void set_grid(lbm_sim* s, int seg_rows) {
-    const lbm_params& p = s->p;
-    Grid& g = s->g;
+void fill_grid(const lbm_params& p, const Layout& L, int seg_rows, Grid& g) {
     g.Nx = p.Nx;
     g.Ny = p.Ny;
-    g.pitch = s->L.pitch;
-    g.rows = s->L.rows;
+    g.pitch = L.pitch;
+    g.rows = L.rows;
     g.periodic_y = (p.flags & LBM_PERIODIC_Y) ? 1 : 0;
     g.y_first = g.periodic_y ? 0 : 1;
-    g.plane = (unsigned)s->L.plane;
+    g.plane = (unsigned)L.plane;
     g.n_strips = (p.Nx + lbmk::kOwned - 1) / lbmk::kOwned;
     g.seg_rows = std::max(1, std::min(seg_rows, g.rows));
     g.n_segs = (g.rows + g.seg_rows - 1) / g.seg_rows;
     g.n_units = g.n_strips * g.n_segs;
     const int nb = (g.n_units + lbmk::kWavesPerBlock - 1) / lbmk::kWavesPerBlock;
     g.n_blocks_pad = (nb + 7) / 8 * 8;
-    s->seg_rows = g.seg_rows;
 }
 
-void set_phys(lbm_sim* s) {
-    const lbm_params& p = s->p;
-    Phys& k = s->k;
+void fill_phys(const lbm_params& p, Phys& k) {
     std::memset(&k, 0, sizeof(k));
     const double kap = kappa_of(p.omega);
     k.rho_ref = p.rho_ref;
@@ -286,6 +291,8 @@ void set_phys(lbm_sim* s) {
     k.inv_drho = (p.rho_l != p.rho_g) ? 1.0 / (p.rho_l - p.rho_g) : 0.0;
     k.inv_Cv = 1.0 / p.C_v;
     k.lambda = p.lambda;
+    k.g_osc = p.g_osc;
+    k.period = p.period;
     k.g_x = p.g_x;
     k.g_y = p.g_y;
     k.rho_v = p.rho_v;
@@ -293,26 +300,61 @@ void set_phys(lbm_sim* s) {
     k.rkB1 = p.a * kap * (1.0 + kap) / std::sqrt(p.T_c);
     k.rkB2 = p.a * kap * kap / p.T_c;
     k.flags = p.flags;
+    auto fillr = [&](auto& r) {
+        using T = std::remove_reference_t<decltype(r.b)>;
+        r.s_rho = (T)k.s_rho;
+        r.s_e = (T)k.s_e;
+        r.s_z = (T)k.s_z;
+        r.s_j = (T)k.s_j;
+        r.s_q = (T)k.s_q;
+        r.c_e = (T)k.c_e;
+        r.c_z = (T)k.c_z;
+        r.b = (T)k.b;
+        r.rkA = (T)k.rkA;
+        r.rkB1 = (T)k.rkB1;
+        r.rkB2 = (T)k.rkB2;
+        r.inv_Cv = (T)k.inv_Cv;
+        r.lambda = (T)k.lambda;
+        r.T_ref = (T)k.T_ref;
+        r.dT_wall = (T)k.dT_wall;
+        r.rho_ref = (T)k.rho_ref;
+        r.rho_v = (T)k.rho_v;
+        r.g_x = (T)k.g_x;
+        r.g_y = (T)k.g_y;
+        r.rho_g = (T)k.rho_g;
+        r.inv_drho = (T)k.inv_drho;
+        r.tau_g = (T)k.tau_g;
+        r.dtau = (T)k.dtau;
+    };
+    fillr(k.rf);
+    fillr(k.rd);
 }
 
-double drive_at(const lbm_params& p, int64_t n) {
-    if (!(p.period > 0.0)) return 0.0;
-    return p.g_osc * std::sin(2.0 * M_PI * (double)n / p.period);
+}  // namespace lbmhost
+
+namespace {
+
+using lbmhost::default_seg_rows;
+
+void set_grid(lbm_sim* s, int seg_rows) {
+    lbmhost::fill_grid(s->p, s->L, seg_rows, s->g);
+    s->seg_rows = s->g.seg_rows;
 }
+
+void set_phys(lbm_sim* s) { lbmhost::fill_phys(s->p, s->k); }
 
 hipError_t enqueue_step(lbm_sim* s) {
-    s->k.drive = drive_at(s->p, s->n);
     const int fa = s->fcur, fb = 1 - s->fcur;
     const int ta = s->tcur, tb = (s->p.flags & LBM_FREEZE_T) ? s->tcur : 1 - s->tcur;
     hipError_t e;
     if (s->p.precision == LBM_FP64) {
         lbmk::Bufs<double> b{s->f<double>(fa), s->f<double>(fb), nullptr, nullptr,
                              s->T<double>(ta), s->T<double>(tb)};
-        e = lbmk::launch_step_f64(s->g, s->k, b, s->stream);
+        e = lbmk::launch_step_f64(s->g, s->k, b, s->n, s->stream);
     } else {
         lbmk::Bufs<float> b{s->f<float>(fa), s->f<float>(fb), s->lo(fa), s->lo(fb),
                             s->T<float>(ta), s->T<float>(tb)};
-        e = lbmk::launch_step_f32(s->g, s->k, b, s->p.precision == LBM_FP32_DEV_MASSEXACT,
+        e = lbmk::launch_step_f32(s->g, s->k, b, s->p.precision == LBM_FP32_DEV_MASSEXACT, s->n,
                                   s->stream);
     }
     if (e != hipSuccess) return e;
@@ -323,14 +365,13 @@ hipError_t enqueue_step(lbm_sim* s) {
 }
 
 hipError_t enqueue_moments(lbm_sim* s) {
-    s->k.drive = drive_at(s->p, s->n);
     if (s->p.precision == LBM_FP64)
         return lbmk::launch_moments_f64(s->g, s->k, s->f<double>(s->fcur), s->T<double>(s->tcur),
                                         s->scr(), s->mom(0), s->mom(1), s->mom(2), s->mom(3),
-                                        s->stream);
+                                        s->n, s->stream);
     return lbmk::launch_moments_f32(s->g, s->k, s->f<float>(s->fcur), s->lo(s->fcur),
                                     s->T<float>(s->tcur), s->scr(), s->mom(0), s->mom(1),
-                                    s->mom(2), s->mom(3), s->stream);
+                                    s->mom(2), s->mom(3), s->n, s->stream);
 }
 
 size_t state_payload(const lbm_sim* s) {
@@ -373,6 +414,7 @@ void lbm_params_default(lbm_params* p) {
     p->lambda = 0.25;
     p->g_osc = 1e-6;
     p->period = 2000.0;
+    p->rho_v = -1.0;
     p->precision = LBM_FP32_DEV;
     p->flags = 0;
 }
@@ -396,6 +438,20 @@ lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_g, dou
     return LBM_OK;
 }
 
+lbm_status lbm_eos_pressure(const lbm_params* p, double rho, double T, double* P, double* psi) {
+    if (!p) return fail(LBM_EINVAL, "null params");
+    if (!(rho > 0.0 && p->b * rho < 1.0 && T > 0.0)) return fail(LBM_EINVAL, "rho or T out of range");
+    if (p->G == 0.0) return fail(LBM_EINVAL, "G must be nonzero");
+    double Tc = p->T_c, rc;
+    if (!(Tc > 0.0)) critical_point(p->a, p->b, p->R, &rc, &Tc);
+    Eos E{p->a, p->b, p->R, kappa_of(p->omega), Tc};
+    const double pe = E.P(rho, T);
+    const double arg = 2.0 * (pe - rho / 3.0) / p->G;
+    if (P) *P = pe;
+    if (psi) *psi = arg > 0.0 ? std::sqrt(arg) : 0.0;
+    return LBM_OK;
+}
+
 lbm_status lbm_params_resolve(lbm_params* p) {
     if (!p) return fail(LBM_EINVAL, "null params");
     if (!(p->a > 0 && p->b > 0 && p->R > 0)) return fail(LBM_EINVAL, "EOS constants must be positive");
@@ -405,15 +461,16 @@ lbm_status lbm_params_resolve(lbm_params* p) {
     }
     if (!(p->T_0 > 0.0)) p->T_0 = 0.86 * p->T_c;
     if (!(p->T_w > 0.0)) p->T_w = 0.80 * p->T_c;
-    if (!(p->rho_g > 0.0) || !(p->rho_l > 0.0) || !(p->rho_v > 0.0)) {
-        double g, l, ps;
+    double g = 0.0;
+    if (!(p->rho_g > 0.0) || !(p->rho_l > 0.0) || p->rho_v < 0.0 || !(p->rho_ref > 0.0)) {
+        double l, ps;
         lbm_status st = lbm_eos_coexistence(p, p->T_0, &g, &l, &ps);
         if (st != LBM_OK) return st;
         if (!(p->rho_g > 0.0)) p->rho_g = g;
         if (!(p->rho_l > 0.0)) p->rho_l = l;
-        if (!(p->rho_v > 0.0)) p->rho_v = g;
+        if (p->rho_v < 0.0) p->rho_v = g;
     }
-    if (!(p->rho_ref > 0.0)) p->rho_ref = p->rho_v;
+    if (!(p->rho_ref > 0.0)) p->rho_ref = p->rho_v > 0.0 ? p->rho_v : g;
     return LBM_OK;
 }
 
@@ -547,10 +604,10 @@ lbm_status lbm_reduce(lbm_sim* s, double out[5]) {
 
 lbm_status lbm_destroy(lbm_sim* s) {
     if (!s) return LBM_OK;
-    hipSetDevice(s->dev);
-    if (s->stream) hipStreamSynchronize(s->stream);
-    if (s->owns_mem && s->base) hipFree(s->base);
-    if (s->owns_stream && s->stream) hipStreamDestroy(s->stream);
+    (void)hipSetDevice(s->dev);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->owns_mem && s->base) (void)hipFree(s->base);
+    if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return LBM_OK;
 }
@@ -696,12 +753,43 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps_per_trial, double* best_ms) {
         if (e == hipSuccess) e = restore();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (ev0) hipEventDestroy(ev0);
-    if (ev1) hipEventDestroy(ev1);
-    hipFree(snap);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipFree(snap);
     set_grid(s, best_seg);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "autotune: %s", hipGetErrorString(e));
     if (best_ms) *best_ms = best;
+    return LBM_OK;
+}
+
+lbm_status lbm_bandwidth_probe(size_t bytes, int32_t iters, double* gbps, double* ms_per_copy) {
+    if (bytes < 16 || iters < 1) return fail(LBM_EINVAL, "bytes >= 16 and iters >= 1 needed");
+    bytes = bytes / 16 * 16;
+    void *a = nullptr, *b = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipStreamCreate(&st);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, bytes, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = lbmk::launch_copy(a, b, bytes, st);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < iters && e == hipSuccess; ++i) e = lbmk::launch_copy(a, b, bytes, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "bandwidth probe: %s", hipGetErrorString(e));
+    const double per = ms / iters;
+    if (gbps) *gbps = 2.0 * (double)bytes / (per * 1e-3) / 1e9;
+    if (ms_per_copy) *ms_per_copy = per;
     return LBM_OK;
 }
 

@@ -57,9 +57,19 @@ _lib = None
 
 
 def lib():
-    """Load the HIP library (raises if it has not been built)."""
+    """Load the HIP library (raises if it has not been built).
+
+    PyTorch-ROCm carries its own HIP runtime.  Importing torch first makes the
+    dynamic loader bind this library to that same runtime, so a process that
+    also uses torch (for device memory, streams or events) holds a single HIP
+    runtime; loading the system runtime first would leave torch unable to
+    initialise the GPU."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("HIP library %s is not built; run "
                                "`python -m paper_1803_01756_amd.build`" % LIB_PATH)
@@ -71,6 +81,7 @@ def lib():
             "lbm_params_resolve": (C.c_int, [P]),
             "lbm_eos_critical": (C.c_int, [C.c_double, C.c_double, C.c_double, dp, dp]),
             "lbm_eos_coexistence": (C.c_int, [P, C.c_double, dp, dp, dp]),
+            "lbm_eos_pressure": (C.c_int, [P, C.c_double, C.c_double, dp, dp]),
             "lbm_workspace_bytes": (C.c_size_t, [P]),
             "lbm_create": (C.c_int, [P, dp, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "lbm_step": (C.c_int, [vp, C.c_int64]),
@@ -87,6 +98,22 @@ def lib():
             "lbm_set_launch": (C.c_int, [vp, C.c_int32]),
             "lbm_get_launch": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "lbm_autotune": (C.c_int, [vp, C.c_int32, dp]),
+            "lbm_bandwidth_probe": (C.c_int, [C.c_size_t, C.c_int32, dp, dp]),
+            "lbm_pool_footprint": (C.c_size_t, [P]),
+            "lbm_pool_create": (C.c_int, [C.c_size_t, vp, C.POINTER(vp)]),
+            "lbm_pool_admit": (C.c_int, [vp, P, dp, C.c_int64, C.POINTER(C.c_int32)]),
+            "lbm_pool_run": (C.c_int, [vp, C.c_int32]),
+            "lbm_pool_poll": (C.c_int, [vp, C.POINTER(C.c_int32), C.c_int32,
+                                        C.POINTER(C.c_int32)]),
+            "lbm_pool_moments": (C.c_int, [vp, C.c_int32, dp, dp, dp, dp]),
+            "lbm_pool_release": (C.c_int, [vp, C.c_int32]),
+            "lbm_pool_destroy": (C.c_int, [vp]),
+            "lbm_pool_info": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_size_t),
+                                        C.POINTER(C.c_size_t)]),
+            "lbm_pool_slot_time": (C.c_int64, [vp, C.c_int32]),
+            "lbm_pool_set_launch": (C.c_int, [vp, C.c_int32]),
+            "lbm_pool_synchronize": (C.c_int, [vp]),
+            "lbm_pool_wait": (C.c_int, [vp, C.c_int32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -99,10 +126,14 @@ def lib():
 def exported_symbols():
     """Names the header declares; the CPU tests check the library has them."""
     return ["lbm_params_default", "lbm_params_resolve", "lbm_eos_critical",
-            "lbm_eos_coexistence", "lbm_workspace_bytes", "lbm_create", "lbm_step",
+            "lbm_eos_coexistence", "lbm_eos_pressure", "lbm_workspace_bytes", "lbm_create", "lbm_step",
             "lbm_moments", "lbm_reduce", "lbm_synchronize", "lbm_destroy", "lbm_time",
             "lbm_get_params", "lbm_last_error", "lbm_state_bytes", "lbm_save", "lbm_load",
-            "lbm_set_launch", "lbm_get_launch", "lbm_autotune"]
+            "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_bandwidth_probe",
+            "lbm_pool_footprint", "lbm_pool_create", "lbm_pool_admit", "lbm_pool_run",
+            "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_release", "lbm_pool_destroy",
+            "lbm_pool_info", "lbm_pool_slot_time", "lbm_pool_set_launch",
+            "lbm_pool_synchronize", "lbm_pool_wait"]
 
 
 def _check(st: int):
@@ -142,6 +173,13 @@ def lbm_eos_coexistence(p: lbm_params, T: float):
     g, l, ps = C.c_double(), C.c_double(), C.c_double()
     _check(lib().lbm_eos_coexistence(C.byref(p), T, C.byref(g), C.byref(l), C.byref(ps)))
     return g.value, l.value, ps.value
+
+
+def lbm_eos_pressure(p: lbm_params, rho: float, T: float):
+    """(P_EOS, psi) at (rho, T)."""
+    P, ps = C.c_double(), C.c_double()
+    _check(lib().lbm_eos_pressure(C.byref(p), rho, T, C.byref(P), C.byref(ps)))
+    return P.value, ps.value
 
 
 def lbm_workspace_bytes(p: lbm_params) -> int:
@@ -225,6 +263,13 @@ def lbm_autotune(h: int, steps_per_trial: int = 10) -> float:
     return ms.value
 
 
+def lbm_bandwidth_probe(nbytes: int, iters: int = 20):
+    """(GB/s counting read + write, ms per copy) of a plain device copy."""
+    g, ms = C.c_double(), C.c_double()
+    _check(lib().lbm_bandwidth_probe(int(nbytes), int(iters), C.byref(g), C.byref(ms)))
+    return g.value, ms.value
+
+
 class Sim:
     """One simulation.  With ``torch_memory=True`` the device workspace is a
     torch tensor and the work is ordered on torch's current stream."""
@@ -293,3 +338,77 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---- slot pool (batched and served runs) ------------------------------------
+def lbm_pool_footprint(p: lbm_params) -> int:
+    return int(lib().lbm_pool_footprint(C.byref(p)))
+
+
+class Pool:
+    """Wrapper of the lbm_pool_* calls.  ``admit`` returns the slot id or
+    None when the footprint does not fit under the cap."""
+
+    def __init__(self, cap_bytes: int, torch_stream: bool = False):
+        stream = 0
+        if torch_stream:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        _check(lib().lbm_pool_create(int(cap_bytes), C.c_void_p(stream or None), C.byref(h)))
+        self.h = h.value
+
+    def admit(self, p: lbm_params, rho0, nsteps: int):
+        r = None if rho0 is None else np.ascontiguousarray(rho0, dtype=np.float64)
+        slot = C.c_int32()
+        st = lib().lbm_pool_admit(C.c_void_p(self.h), C.byref(p), _dp(r), int(nsteps),
+                                  C.byref(slot))
+        if st == LBM_ENOMEM:
+            return None
+        _check(st)
+        return slot.value
+
+    def run(self, chunk_steps: int):
+        _check(lib().lbm_pool_run(C.c_void_p(self.h), int(chunk_steps)))
+
+    def poll(self, max_n: int = 1024):
+        buf = (C.c_int32 * max_n)()
+        n = C.c_int32()
+        _check(lib().lbm_pool_poll(C.c_void_p(self.h), buf, max_n, C.byref(n)))
+        return list(buf[:n.value])
+
+    def moments(self, slot: int, Nx: int, Ny: int):
+        outs = [np.empty((Ny, Nx)) for _ in range(4)]
+        _check(lib().lbm_pool_moments(C.c_void_p(self.h), int(slot), *[_dp(o) for o in outs]))
+        return tuple(outs)
+
+    def release(self, slot: int):
+        _check(lib().lbm_pool_release(C.c_void_p(self.h), int(slot)))
+
+    def info(self):
+        a, u, c = C.c_int32(), C.c_size_t(), C.c_size_t()
+        _check(lib().lbm_pool_info(C.c_void_p(self.h), C.byref(a), C.byref(u), C.byref(c)))
+        return a.value, u.value, c.value
+
+    def slot_time(self, slot: int) -> int:
+        return int(lib().lbm_pool_slot_time(C.c_void_p(self.h), int(slot)))
+
+    def set_launch(self, seg_rows: int):
+        _check(lib().lbm_pool_set_launch(C.c_void_p(self.h), int(seg_rows)))
+
+    def synchronize(self):
+        _check(lib().lbm_pool_synchronize(C.c_void_p(self.h)))
+
+    def wait(self, max_pending: int):
+        _check(lib().lbm_pool_wait(C.c_void_p(self.h), int(max_pending)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_pool_destroy(C.c_void_p(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,185 @@
+"""GPU parity beyond the default channel, through the C-ABI.
+
+* Edge grids: strips narrower than a wave, widths around the 54-column strip
+  boundary, channels with a single or two fluid rows.
+* Flags: periodic box, single-phase flow with gravity, frozen temperature.
+* Full sizes: the 2048 x 256 and 8192 x 512 channels started from a density
+  field that repeats every 128 columns.  The step has no cross-node
+  reduction, so every 128-column tile must stay bitwise identical, and one
+  tile must match the oracle run on a 128-column periodic channel (the same
+  problem).
+* Mass: the mass-exact storage conserves total mass to FP64 rounding.
+* Checkpoints, reductions, torch-provided memory, non-finite detection.
+"""
+import numpy as np
+import pytest
+
+from helpers import field_errors, fluid_mask, to_oracle
+from paper_1803_01756_amd import configs, inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    print("\n[case] %s" % name, flush=True)
+
+
+def _gpu(p, rho0, steps, **kw):
+    s = lbm.Sim(p, rho0, **kw)
+    s.step(steps)
+    out = s.moments()
+    s.close()
+    return out
+
+
+def _oracle(orc, p, rho0, steps):
+    o = orc.Sim(to_oracle(orc, p), rho0)
+    o.step(steps)
+    return o.moments()
+
+
+@pytest.mark.parametrize("Nx,Ny", [(3, 4), (20, 5), (54, 6), (55, 7), (65, 9), (130, 12),
+                                   (109, 40)])
+def test_edge_grids_fp64(orc, Nx, Ny):
+    _case("edge grid %dx%d fp64" % (Nx, Ny))
+    p = configs.channel_params(Nx, Ny, 120.0, 0.8, 1e-5, 50.0, lbm.LBM_FP64)
+    rho0 = configs.initial_density(p, seed=Nx * 100 + Ny)
+    e = field_errors(_gpu(p, rho0, 30), _oracle(orc, p, rho0, 30), fluid_mask(Nx, Ny))
+    print(e, flush=True)
+    assert e["rho"] < 1e-11 and e["u"] < 1e-9 and e["T"] < 1e-11
+
+
+@pytest.mark.parametrize("flags", [lbm.LBM_PERIODIC_Y, lbm.LBM_SINGLE_PHASE,
+                                   lbm.LBM_FREEZE_T, lbm.LBM_PERIODIC_Y | lbm.LBM_FREEZE_T])
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+def test_flags_parity(orc, flags, precision):
+    _case("flags=%d precision=%d 60x20" % (flags, precision))
+    extra = {}
+    if flags & lbm.LBM_SINGLE_PHASE:
+        extra = dict(g_x=1e-5, g_y=-2e-6, rho_v=0.0)
+    p = configs.channel_params(60, 20, 120.0, 0.8, 1e-5, 100.0, precision, flags, **extra)
+    rho0 = inputs.density_field(60, 20, p.rho_g, 0.01, 11)
+    e = field_errors(_gpu(p, rho0, 60), _oracle(orc, p, rho0, 60),
+                     fluid_mask(60, 20, bool(flags & lbm.LBM_PERIODIC_Y)))
+    print(e, flush=True)
+    tol = (1e-11, 1e-9, 1e-11) if precision == lbm.LBM_FP64 else (1e-5, 1e-5, 1e-5)
+    assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
+
+
+@pytest.mark.parametrize("which", ["2048x256", "8192x512"])
+def test_full_size_tiled_parity(orc, which):
+    _case("full size %s fp32, tiled start, 100 steps" % which)
+    p = (configs.single_gpu_channel(90.0) if which == "2048x256" else configs.large_channel())
+    tile = 128
+    r_tile = inputs.density_field(tile, p.Ny, p.rho_v, 0.01, 5)
+    rho0 = np.tile(r_tile, (1, p.Nx // tile))
+    s = lbm.Sim(p, rho0)
+    s.step(100)
+    g = s.moments()
+    s.close()
+    for a in g:
+        t0 = a[:, :tile]
+        for k in range(1, p.Nx // tile):
+            assert np.array_equal(a[:, k * tile:(k + 1) * tile], t0), k
+    q = lbm.lbm_params.from_buffer_copy(p)
+    q.Nx = tile
+    r = _oracle(orc, q, r_tile, 100)
+    e = field_errors([a[:, :tile] for a in g], r, fluid_mask(tile, p.Ny))
+    print(e, flush=True)
+    assert e["rho"] < 1e-5 and e["u"] < 1e-5 and e["T"] < 1e-5
+
+
+def test_mass_exact_storage_conserves_mass():
+    _case("mass drift 256x64, 3000 steps")
+    drift = {}
+    for prec in (lbm.LBM_FP32_DEV_MASSEXACT, lbm.LBM_FP32_DEV, lbm.LBM_FP64):
+        p = configs.channel_params(256, 64, 75.0, 0.78, 2e-6, 400.0, prec)
+        rho0 = configs.initial_density(p, seed=2)
+        s = lbm.Sim(p, rho0)
+        m0 = s.reduce()[0]
+        s.step(3000)
+        m1 = s.reduce()[0]
+        s.close()
+        drift[prec] = abs(m1 - m0) / m0
+    print(drift, flush=True)
+    assert drift[lbm.LBM_FP32_DEV_MASSEXACT] < 1e-13
+    assert drift[lbm.LBM_FP64] < 1e-13
+
+
+def test_checkpoint_roundtrip_bitwise():
+    _case("checkpoint 128x32")
+    for prec in (lbm.LBM_FP32_DEV, lbm.LBM_FP64, lbm.LBM_FP32_DEV_MASSEXACT):
+        p = configs.oracle_size_channel(prec)
+        rho0 = configs.initial_density(p, seed=4)
+        a = lbm.Sim(p, rho0)
+        a.step(40)
+        blob = a.save()
+        a.step(35)
+        ref = a.moments()
+        b = lbm.Sim(p, None)
+        b.load(blob)
+        assert b.n == 40
+        b.step(35)
+        out = b.moments()
+        for x, y in zip(out, ref):
+            assert np.array_equal(x, y)
+        a.close()
+        b.close()
+
+
+def test_reduce_matches_moments():
+    _case("reduce vs moments")
+    p = configs.oracle_size_channel()
+    rho0 = configs.initial_density(p, seed=6)
+    s = lbm.Sim(p, rho0)
+    s.step(50)
+    rho, ux, uy, T = s.moments()
+    red = s.reduce()
+    s.close()
+    m = fluid_mask(p.Nx, p.Ny)
+    assert abs(red[0] - rho[m].sum()) < 1e-12 * red[0]
+    assert abs(red[1] - (rho * ux)[m].sum()) < 1e-12 * np.abs(rho * ux)[m].sum()
+    assert abs(red[3] - (rho * p.C_v * T)[m].sum()) < 1e-12 * red[3]
+    assert red[4] == 0
+
+
+def test_torch_workspace_matches_library_memory():
+    _case("torch workspace")
+    p = configs.oracle_size_channel()
+    rho0 = configs.initial_density(p, seed=8)
+    a = _gpu(p, rho0, 30)
+    b = _gpu(p, rho0, 30, torch_memory=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_nonfinite_state_is_reported():
+    _case("non-finite detection")
+    p = configs.oracle_size_channel()
+    s = lbm.Sim(p, configs.initial_density(p, seed=9))
+    blob = bytearray(s.save())
+    # overwrite one stored population (bytes of the f plane) with a NaN
+    hdr = len(blob) - (9 + 1) * 128 * 30 * 4
+    blob[hdr + 4 * 1000: hdr + 4 * 1001] = np.array([np.nan], dtype=np.float32).tobytes()
+    s.load(bytes(blob))
+    s.step(3)
+    with pytest.raises(lbm.LBMError) as ei:
+        s.reduce()
+    assert ei.value.status == lbm.LBM_EUNSTABLE
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+def test_parity_2000_steps(orc, precision):
+    """The oracle-size channel over its full 2000 steps (one third of a drive
+    period past the first peak).  FP64 stays at rounding level; FP32
+    deviation storage accumulates its rounding over 2000 steps."""
+    _case("128x32 2000 steps precision=%d" % precision)
+    p = configs.oracle_size_channel(precision)
+    rho0 = configs.initial_density(p, seed=1)
+    e = field_errors(_gpu(p, rho0, 2000), _oracle(orc, p, rho0, 2000), fluid_mask(p.Nx, p.Ny))
+    print(e, flush=True)
+    if precision == lbm.LBM_FP64:
+        assert e["rho"] < 1e-10 and e["u"] < 1e-8 and e["T"] < 1e-10
+    else:
+        assert e["rho"] < 1e-4 and e["u"] < 1e-3 and e["T"] < 1e-4

@@ -1,0 +1,89 @@
+"""GPU tests of the slot pool (batched and served runs) through the C-ABI.
+
+A channel stepped inside a batch, admitted while other channels are already
+running, must give bitwise the result of the same channel run alone: the
+batched launch runs the same per-node arithmetic, only the work list
+differs.  Admission must respect the byte cap."""
+import numpy as np
+import pytest
+
+from paper_1803_01756_amd import configs, lbm, serve
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    print("\n[case] %s" % name, flush=True)
+
+
+def _chan(Nx, Ny, ca, tw, g, per, seed, flags=0):
+    p = configs.channel_params(Nx, Ny, ca, tw, g, per, lbm.LBM_FP32_DEV, flags)
+    return p, configs.initial_density(p, seed)
+
+
+def _alone(p, rho0, steps):
+    s = lbm.Sim(p, rho0)
+    s.step(steps)
+    out = s.moments()
+    s.close()
+    return out
+
+
+def test_pool_staggered_admission_equals_alone():
+    _case("pool staggered admission")
+    chans = [_chan(300, 34, 120.0, 0.80, 2e-6, 400.0, 1), _chan(140, 48, 150.0, 0.78, 5e-6, 300.0, 2),
+             _chan(64, 20, 100.0, 0.84, 1e-6, 700.0, 3),
+             _chan(515, 40, 130.0, 0.80, 3e-6, 250.0, 4, lbm.LBM_FREEZE_T)]
+    steps = [400, 250, 330, 200]
+    pool = lbm.Pool(1 << 30)
+    sl = [pool.admit(chans[0][0], chans[0][1], steps[0]), pool.admit(chans[1][0], chans[1][1], steps[1])]
+    pool.run(150)
+    sl.append(pool.admit(chans[2][0], chans[2][1], steps[2]))
+    pool.run(100)
+    sl.append(pool.admit(chans[3][0], chans[3][1], steps[3]))
+    done = set()
+    for _ in range(20):
+        pool.run(90)
+        pool.wait(0)
+        done |= set(pool.poll())
+        if len(done) == 4:
+            break
+    assert done == set(sl)
+    for (p, r0), s, n in zip(chans, sl, steps):
+        assert pool.slot_time(s) == n
+        got = pool.moments(s, p.Nx, p.Ny)
+        ref = _alone(p, r0, n)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+    pool.close()
+
+
+def test_pool_admission_by_footprint():
+    _case("pool cap")
+    a, b = _chan(256, 32, 120.0, 0.8, 1e-6, 500.0, 5), _chan(512, 64, 120.0, 0.8, 1e-6, 500.0, 6)
+    fa, fb = lbm.lbm_pool_footprint(a[0]), lbm.lbm_pool_footprint(b[0])
+    assert fa >= 256 * 30 * 80 and fb >= 512 * 62 * 80
+    pool = lbm.Pool(fa + fb - 1)
+    sa = pool.admit(a[0], a[1], 10)
+    assert sa is not None
+    assert pool.admit(b[0], b[1], 10) is None
+    pool.run(10)
+    pool.wait(0)
+    pool.release(sa)
+    sb = pool.admit(b[0], b[1], 10)
+    assert sb is not None
+    assert pool.info()[1] == fb
+    pool.close()
+
+
+def test_served_stream_results_equal_alone():
+    _case("served stream")
+    reqs = serve.make_requests(10, rate=40.0, steps_scale=0.02)
+    pool = lbm.Pool(8 << 30)
+    serve.serve(reqs, pool, chunk=100)
+    pool.close()
+    assert all(r.finished > r.arrival for r in reqs)
+    for r in reqs[:3]:
+        ref = _alone(r.params, r.rho0, r.steps)
+        for a, b in zip(r.result, ref):
+            assert np.array_equal(a, b)

@@ -1,0 +1,120 @@
+"""CPU tests of the serving loop's scheduling (admission by footprint, slot
+reuse, completion order, latency accounting) against a fake pool with a
+scripted cost per chunk and a simulated clock: no GPU involved."""
+import numpy as np
+
+from paper_1803_01756_amd import serve
+
+
+class FakeParams:
+    def __init__(self, Nx, Ny):
+        self.Nx, self.Ny, self.flags = Nx, Ny, 0
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+class FakePool:
+    """Footprint = Nx*Ny bytes; a chunk advances every active slot by
+    `chunk` steps and costs `cost_per_node_step` seconds per node-step."""
+
+    def __init__(self, cap, clock, cost=1e-9):
+        self.cap, self.used, self.clock, self.cost = cap, 0, clock, cost
+        self.slots, self.free_ids, self.next_id = {}, [], 0
+        self.admit_log, self.max_used = [], 0
+
+    def admit(self, p, rho0, steps):
+        need = p.Nx * p.Ny
+        if self.used + need > self.cap:
+            return None
+        sid = self.free_ids.pop() if self.free_ids else self.next_id
+        if sid == self.next_id:
+            self.next_id += 1
+        self.slots[sid] = dict(p=p, left=steps, need=need, reported=False)
+        self.used += need
+        self.max_used = max(self.max_used, self.used)
+        self.admit_log.append(sid)
+        return sid
+
+    def run(self, chunk):
+        work = 0
+        for s in self.slots.values():
+            take = min(chunk, s["left"])
+            s["left"] -= take
+            work += take * s["need"]
+        self.clock.t += work * self.cost
+
+    def wait(self, k):
+        pass
+
+    def poll(self):
+        out = [i for i, s in self.slots.items() if s["left"] == 0 and not s["reported"]]
+        for i in out:
+            self.slots[i]["reported"] = True
+        return out
+
+    def moments(self, sid, Nx, Ny):
+        return ("result", sid)
+
+    def release(self, sid):
+        self.used -= self.slots.pop(sid)["need"]
+        self.free_ids.append(sid)
+
+
+def _reqs(n, rate, sizes, steps, seed=0):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    return [serve.Request(rid=k, arrival=float(t[k]), params=FakeParams(*sizes[k % len(sizes)]),
+                          rho0=None, steps=steps[k % len(steps)]) for k in range(n)]
+
+
+def test_every_request_completes_with_nonnegative_latency():
+    clk = FakeClock()
+    pool = FakePool(cap=10 ** 6, clock=clk)
+    reqs = _reqs(50, 20.0, [(256, 32), (512, 64), (1024, 128)], [2000, 5000, 20000])
+    serve.serve(reqs, pool, chunk=500, clock=clk, sleep=clk.sleep)
+    assert all(r.finished >= r.admitted >= r.arrival for r in reqs)
+    assert all(r.result == ("result", r.slot) for r in reqs)
+    st = serve.latency_stats(reqs)
+    assert st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_admission_respects_cap_and_reuses_slots():
+    clk = FakeClock()
+    cap = 2 * 1024 * 128  # room for two of the largest
+    pool = FakePool(cap=cap, clock=clk)
+    reqs = _reqs(30, 50.0, [(1024, 128)], [3000])
+    serve.serve(reqs, pool, chunk=500, clock=clk, sleep=clk.sleep)
+    assert pool.max_used <= cap
+    assert max(pool.admit_log) <= 1  # only two slot ids ever needed
+    # with the cap binding, requests queue: admission waits past arrival
+    assert any(r.admitted > r.arrival + 1e-9 for r in reqs)
+
+
+def test_fifo_admission_order():
+    clk = FakeClock()
+    pool = FakePool(cap=3 * 256 * 32, clock=clk)
+    reqs = _reqs(20, 100.0, [(256, 32)], [1000, 4000])
+    serve.serve(reqs, pool, chunk=250, clock=clk, sleep=clk.sleep)
+    adm = [r.admitted for r in sorted(reqs, key=lambda r: r.arrival)]
+    assert adm == sorted(adm)
+
+
+def test_late_arrivals_join_a_running_batch():
+    """Continuous batching: a request arriving while others run is admitted
+    before those finish (not after the batch drains)."""
+    clk = FakeClock()
+    pool = FakePool(cap=10 ** 7, clock=clk, cost=1e-8)
+    reqs = [serve.Request(0, 0.0, FakeParams(1024, 128), None, 20000),
+            serve.Request(1, 0.05, FakeParams(256, 32), None, 2000)]
+    serve.serve(reqs, pool, chunk=500, clock=clk, sleep=clk.sleep)
+    assert reqs[1].admitted < reqs[0].finished
+    assert reqs[1].finished < reqs[0].finished
