@@ -1,0 +1,108 @@
+"""Droplet statistics of the cold-wall condensation channel on a 512 x 64
+crop, from the FP64 oracle.
+
+TEST INFRASTRUCTURE: runs only the oracle.  Writes
+tests/golden/crop_512x64_droplets.json, against which the GPU run of the same
+crop (same parameters and seed) is compared.  After nucleation the droplet
+positions depend on rounding, so the comparison is on statistics: the number
+of droplets on each plate, their mean spacing and the condensed volume.
+
+Set-up (the 8192 x 512 workload cut to 512 x 64): T_0 = 0.86 Tc, plates at
+0.78 Tc, wall density fraction for a 75 degree contact angle, drive
+2e-6 sin(2 pi n / 4000), saturated vapour with +-1 % noise (seed 1),
+50000 steps, statistics every 10000 steps.  A droplet is a connected set
+(4-neighbour, periodic in x) of nodes with rho > (rho_l + rho_g)/2 that
+touches the first fluid row above the lower plate or below the upper plate.
+
+    python oracle/crop_droplet_stats.py
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+NX, NY, STEPS, EVERY, SEED = 512, 64, 50000, 10000, 1
+WALL_FRACTION_75 = None  # filled from the calibration table
+
+
+def droplet_stats(rho, thr):
+    """Count, mean spacing and condensed volume of droplets on each plate
+    (plain flood fill; rho indexed [y, x] with the plate rows included)."""
+    ny, nx = rho.shape
+    liq = rho > thr
+    liq[0] = liq[-1] = False
+    lab = np.zeros(liq.shape, dtype=np.int64)
+    n = 0
+    for y in range(1, ny - 1):
+        for x in range(nx):
+            if liq[y, x] and lab[y, x] == 0:
+                n += 1
+                stack = [(y, x)]
+                lab[y, x] = n
+                while stack:
+                    cy, cx = stack.pop()
+                    for dy, dx in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                        yy, xx = cy + dy, (cx + dx) % nx
+                        if 1 <= yy <= ny - 2 and liq[yy, xx] and lab[yy, xx] == 0:
+                            lab[yy, xx] = n
+                            stack.append((yy, xx))
+    out = {}
+    for name, row in (("bottom", 1), ("top", ny - 2)):
+        ids = sorted(set(lab[row][lab[row] > 0].tolist()))
+        centres = []
+        for i in ids:
+            xs = np.nonzero((lab == i).any(axis=0))[0]
+            # circular mean of the columns (periodic in x)
+            ang = 2 * np.pi * xs / nx
+            c = (np.arctan2(np.sin(ang).mean(), np.cos(ang).mean()) % (2 * np.pi)) * nx / (2 * np.pi)
+            centres.append(float(c))
+        centres.sort()
+        if len(centres) > 1:
+            gaps = np.diff(centres + [centres[0] + nx])
+            spacing = float(np.mean(gaps))
+        else:
+            spacing = float(nx) if centres else 0.0
+        out[name] = dict(count=len(ids), mean_spacing=spacing)
+    out["condensed_nodes"] = int(liq.sum())
+    return out
+
+
+def main():
+    from oracle import oracle as O
+    from paper_1803_01756_amd import inputs
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "contact_angle_table.json")))
+    tab = sorted((r["angle"], r["frac"]) for r in gold["table"] if r["angle"] < 180.0)
+    frac = float(np.interp(75.0, [a for a, _ in tab], [f for _, f in tab]))
+    tc = O.critical()[1]
+    p = O.default_params(Nx=NX, Ny=NY, Tw=0.78 * tc, g_osc=2e-6, period=4000.0)
+    p.Gw = p.G
+    p.psiw = O.psi(p, p.rho_g + frac * (p.rho_l - p.rho_g), p.T0)
+    rho0 = inputs.density_field(NX, NY, p.rho_v, 0.01, SEED)
+    s = O.Sim(p, rho0)
+    thr = 0.5 * (p.rho_l + p.rho_g)
+    hist = []
+    t0 = time.time()
+    m0 = s.moments()[0][1:-1].sum()
+    for k in range(STEPS // EVERY):
+        s.step(EVERY)
+        rho = s.moments()[0]
+        st = droplet_stats(rho, thr)
+        st["step"] = s.n
+        st["mass_rel_drift"] = float(rho[1:-1].sum() / m0 - 1)
+        hist.append(st)
+        print(json.dumps(st), "%.0f s" % (time.time() - t0), flush=True)
+    out = dict(source="oracle/crop_droplet_stats.py (FP64 oracle only)", Nx=NX, Ny=NY, seed=SEED,
+               wall_fraction=frac, Tw_over_Tc=0.78, g_osc=2e-6, period=4000.0, history=hist)
+    path = os.path.join(ROOT, "tests", "golden", "crop_512x64_droplets.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()

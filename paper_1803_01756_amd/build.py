@@ -31,9 +31,11 @@ def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     tmp = LIB + ".tmp%d" % os.getpid()
     # code object v5: accepted by the system ROCm runtime and by the one that
-    # PyTorch-ROCm ships
+    # PyTorch-ROCm ships.  -ffp-contract=on: multiply-adds are fused only
+    # within one source expression, so every copy of the unrolled row loop
+    # rounds alike and results do not depend on the launch shape.
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-mcode-object-version=5",
+           "-mcode-object-version=5", "-ffp-contract=on",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] + srcs
     if verbose:

@@ -285,8 +285,8 @@ __device__ __forceinline__ const PhysR<double>& pr<double>(const Phys& k) { retu
 // MRT collision, Eqs. 6-8, in deviation moments: m'_k = m_k - rho_ref (M w)_k.
 // Returns the post-collision deviations in d (overwritten).
 template <class R>
-__device__ __forceinline__ void collide(R d[9], R drho, R rho, R ux, R uy, R Fx, R Fy, R th,
-                                        R sv, const Phys& k) {
+__device__ __forceinline__ void collide(R d[9], R drho, R rho, R rinv, R ux, R uy, R Fx, R Fy,
+                                        R th, R sv, const Phys& k) {
     const PhysR<R>& c = pr<R>(k);
     const R s_rho = c.s_rho, s_e = c.s_e, s_z = c.s_z, s_j = c.s_j, s_q = c.s_q;
     const R axis = (d[1] + d[2]) + (d[3] + d[4]);
@@ -302,7 +302,6 @@ __device__ __forceinline__ void collide(R d[9], R drho, R rho, R ux, R uy, R Fx,
     m[7] = (d[1] + d[3]) - (d[2] + d[4]);
     m[8] = (d[5] + d[7]) - (d[6] + d[8]);
     const R jx = rho * ux, jy = rho * uy;
-    const R rinv = rcp_r(rho);
     const R j2r = (jx * jx + jy * jy) * rinv;
     R meq[9];
     meq[0] = drho;
@@ -352,12 +351,18 @@ __device__ __forceinline__ void collide(R d[9], R drho, R rho, R ux, R uy, R Fx,
 // B1 = a k (1 + k) rho^2 / (sqrt(Tc) D), B2 = a k^2 rho^2 / (Tc D),
 // D = 1 + 2 b rho - b^2 rho^2, and c = 1 / (rho C_v):
 //   q1 = c div(u) (A - B2), q2 = c div(u) B1, q3 = c lambda.
+// FP32 build: an RK stage moves T by ~1e-4 relative, so sqrt(T) is taken
+// linear about the row's T(n): sqrt(T) = s + (T - T_n)/(2 s), s = sqrt(T_n)
+// (neglected term (T - T_n)^2 / (8 s^3), ~1e-9 relative), which turns the
+// last two terms into -Q1 T - Q0 with Q1 = q1 + q2/(2 s), Q0 = q2 s / 2 and
+// needs one reciprocal square root per row instead of one square root per
+// stage.  The FP64 build keeps the exact sqrt (Q1 = q1, Q0 = 0, q2 kept).
 template <class R>
 struct Coef {
     R ux, uy, q1, q2, q3;
 };
 template <class R>
-__device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, const Phys& k) {
+__device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, const Phys& k) {
     const PhysR<R>& pc = pr<R>(k);
     const R br = pc.b * rho;
     const R omb = (R)1 - br;
@@ -372,6 +377,12 @@ __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, const Ph
     q.q1 = c * divu * (A - pc.rkB2 * r2D);
     q.q2 = c * divu * pc.rkB1 * r2D;
     q.q3 = c * pc.lambda;
+    if (sizeof(R) == 4) {
+        const R rs = (R)__builtin_amdgcn_rsqf((float)Tn);  // 1 / sqrt(T_n)
+        const R sn = Tn * rs;
+        q.q1 = q.q1 + q.q2 * (R)0.5 * rs;  // Q1
+        q.q2 = q.q2 * (R)0.5 * sn;         // Q0
+    }
     return q;
 }
 
@@ -386,7 +397,9 @@ __device__ __forceinline__ R heat_rhs(const Tri<R>& tS, const Tri<R>& tC, const 
     const R dg = (tN.p + tN.m) + (tS.p + tS.m);
     const R lap = ax * ((R)2 / 3) + dg * ((R)1 / 6) - tC.c * ((R)10 / 3);
     const R Tabs = T_ref + tC.c;
-    return -(q.ux * tx + q.uy * ty) + q.q3 * lap - q.q1 * Tabs - q.q2 * sqrt_r(Tabs);
+    const R adv_cond = -(q.ux * tx + q.uy * ty) + q.q3 * lap;
+    if (sizeof(R) == 4) return adv_cond - q.q1 * Tabs - q.q2;
+    return adv_cond - q.q1 * Tabs - q.q2 * sqrt_r(Tabs);
 }
 
 // divergence of u at row y from rows y-1 (uS), y (uC), y+1 (uN)
@@ -467,12 +480,11 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     R tn4 = 0, tn5 = 0;
     // velocity rows k-1, k-2, k-3
     Tri<R> ux1, ux2, ux3, uy1, uy2, uy3;
-    // heat coefficients rows k-2 .. k-5 (cf6, cf7 only pad the window to six
-    // rows, so that it returns to its registers after one six-row trip)
-    Coef<R> cf2, cf3, cf4, cf5, cf6, cf7;
+    // heat coefficients rows k-2 .. k-5
+    Coef<R> cf2, cf3, cf4, cf5;
     // RK stage fields: T1 rows k-2..k-4, T2 rows k-3..k-5, T3 rows k-4..k-6
     Tri<R> t1a, t1b, t1c, t2a, t2b, t2c, t3a, t3b, t3c;
-    R acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0, acc6 = 0, acc7 = 0;  // sum of h's, rows k-2..k-5
+    R acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0;  // sum of the h's, rows k-2 .. k-5
     double drdCur = 0.0, drdPrv = 0.0;         // mass-exact: FP64 deviation density
 
 #pragma unroll
@@ -480,7 +492,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     psi0 = psi1 = psi2 = tri_const<double>(0.0);
     tn0 = tn1 = tn2 = tn3 = tri_const<R>(dTw);
     ux1 = ux2 = ux3 = uy1 = uy2 = uy3 = tri_const<R>(0);
-    cf2 = cf3 = cf4 = cf5 = cf6 = cf7 = Coef<R>{0, 0, 0, 0, 0};
+    cf2 = cf3 = cf4 = cf5 = Coef<R>{0, 0, 0, 0, 0};
     t1a = t1b = t1c = t2a = t2b = t2c = t3a = t3b = t3c = tri_const<R>(dTw);
 
     const unsigned esz = (unsigned)sizeof(S);
@@ -495,23 +507,40 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     const unsigned rowb = (unsigned)g.pitch * esz;
 
     // One row iteration; the loop below calls it six times per trip so that
-    // the row windows (depths 2, 3 and 6) rotate by renaming registers instead
+    // the row windows of depth 2, 3 and 6 rotate by renaming registers instead
     // of moving them (a loop holding DPP operations is not unrolled by the
-    // compiler).  Padding iterations past the segment only read valid rows and
+    // compiler); the depth-4 windows move once per trip.  Padding iterations past the segment only read valid rows and
     // store nothing; launch shapes with seg_rows + 10 a multiple of 6 need none.
+    const int kr_end = yb + kHalo;
+    // raw loads of the current row, issued one iteration ahead
+    S curD[9];
+    S curT;
+    float curLo = 0.0f;
+    {
+        const RowK rS = row_info(ya - kHalo, g);
+        const RowK r0 = rS.fluid ? rS : row_info(g.y_first, g);
+        pull_row_buf<S>(rf_in, g, r0, vx, vm, vp, curD);
+        curT = bload(rT_in, vx, (unsigned)r0.sr * rowb, S(0));
+        if (kMX) curLo = bload(rlo_in, x * 4u, (unsigned)r0.sr * (unsigned)g.pitch * 4u, 0.0f);
+    }
     auto row_iteration = [&](const int kr) {
-        // ------------- stage A: pull row kr, rho, j, psi ------------------
+        // ------------- prefetch: issue the loads of row kr+1 --------------
+        // They complete while this iteration computes; stage A of the next
+        // iteration consumes them.  (Padding iterations past kr_end compute
+        // and load nothing.)
+        const bool live = kr < kr_end;
+        // ------------- stage A: row kr (loaded one iteration ago): rho, j, psi
         const RowK rA = row_info(kr, g);
         Tri<double> psiA;
         R dTA;
-        if (rA.fluid) {
-            S raw[9];
-            pull_row_buf<S>(rf_in, g, rA, vx, vm, vp, raw);
-            const S rawT = bload(rT_in, vx, (unsigned)rA.sr * rowb, S(0));
-            R lo = 0;
-            if (kMX) lo = (R)bload(rlo_in, x * 4u, (unsigned)rA.sr * (unsigned)g.pitch * 4u, 0.0f);
+        if (rA.fluid && live) {
+            pull_row_buf<S>(rf_in, g, rA, vx, vm, vp, curD);
+            curT = bload(rT_in, vx, (unsigned)rA.sr * rowb, S(0));
+            if (kMX) curLo = bload(rlo_in, x * 4u, (unsigned)rA.sr * (unsigned)g.pitch * 4u, 0.0f);
+            const R lo = kMX ? (R)curLo : (R)0;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) dCur[q] = (R)raw[q];
+            for (int q = 0; q < 9; ++q) dCur[q] = (R)curD[q];
+            const S rawT = curT;
             double drd;
             if (kMX) {
                 drd = (double)dCur[0] + (double)lo;
@@ -542,10 +571,16 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         psi0 = psiA;
         tn0 = tri<R>(dTA);
 
+        // Stages whose row lies below the rows the segment needs from them are
+        // skipped (the first iterations of a segment): B needs rows from
+        // ya-4, C from ya-3, D from ya-2, E from ya-1 (each stage widens the
+        // stencil by one row); their window entries are then never read.
+        const bool needB = live && kr - 1 >= ya - 4, needC = live && kr - 2 >= ya - 3;
+        const bool needD = live && kr - 3 >= ya - 2, needE = live && kr - 4 >= ya - 1;
         // ------------- stage B: forces, u, collision on row kr-1 ---------
         const RowK rB = row_info(kr - 1, g);
         Tri<R> uxB, uyB;
-        if (rB.fluid) {
+        if (rB.fluid && needB) {
             double Fxd = 0.0, Fyd = 0.0, Fmx = 0.0, Fmy = 0.0;
             if (!single) {
                 pair_force(psi2, psi1, psi0, k.negG, Fxd, Fyd);
@@ -574,7 +609,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 R dn[9];
 #pragma unroll
                 for (int q = 0; q < 9; ++q) dn[q] = dPrv[q];
-                collide<R>(dn, drPrv, rho, ux, uy, Fx, Fy, th, sv, k);
+                collide<R>(dn, drPrv, rho, rinv, ux, uy, Fx, Fy, th, sv, k);
                 if (own_lane) {
                     const unsigned so = (unsigned)rB.sr * rowb;
                     const unsigned P = g.plane * esz;
@@ -606,9 +641,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             // ------------- stage C: div u, coefficients, h1 on row kr-2 ---
             const RowK rC = row_info(kr - 2, g);
             Tri<R> t1;
-            if (rC.fluid) {
+            if (rC.fluid && needC) {
                 const R dv = div_u<R>(ux3, ux2, ux1, uy3, uy2, uy1);
-                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, k);
+                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, k);
                 const R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
                 acc2 = h1;
                 t1 = tri<R>(tn2.c + (R)0.5 * h1);
@@ -620,7 +655,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             // ------------- stage D: h2 on row kr-3 ------------------------
             const RowK rD = row_info(kr - 3, g);
             Tri<R> t2;
-            if (rD.fluid) {
+            if (rD.fluid && needD) {
                 const R h2 = heat_rhs<R>(t1c, t1b, t1a, cf3, T_ref);
                 acc3 += (R)2 * h2;
                 t2 = tri<R>(tn3.c + (R)0.5 * h2);
@@ -631,7 +666,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             // ------------- stage E: h3 on row kr-4 ------------------------
             const RowK rE = row_info(kr - 4, g);
             Tri<R> t3;
-            if (rE.fluid) {
+            if (rE.fluid && needE) {
                 const R h3 = heat_rhs<R>(t2c, t2b, t2a, cf4, T_ref);
                 acc4 += (R)2 * h3;
                 t3 = tri<R>(tn4 + h3);
@@ -660,13 +695,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         ux2 = ux1;
         uy3 = uy2;
         uy2 = uy1;
-        cf7 = cf6;
-        cf6 = cf5;
         cf5 = cf4;
         cf4 = cf3;
         cf3 = cf2;
-        acc7 = acc6;
-        acc6 = acc5;
         acc5 = acc4;
         acc4 = acc3;
         acc3 = acc2;
@@ -684,8 +715,8 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         drdPrv = drdCur;
 #pragma unroll
         for (int q = 0; q < 9; ++q) dPrv[q] = dCur[q];
+
     };
-    const int kr_end = yb + kHalo;
     for (int kr = ya - kHalo; kr < kr_end; kr += 6) {
         row_iteration(kr);
         row_iteration(kr + 1);
@@ -701,12 +732,22 @@ __device__ __forceinline__ int wave_in_block() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// The FP64 build has its own kernel: it needs about 256 registers and runs
+// one wave per SIMD, the FP32 builds fit three.
 template <class S, bool kMX>
 __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Phys k, Bufs<S> B,
-                                                                     long long n) {
+                                                                        long long n) {
     const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
     if (unit >= g.n_units) return;  // whole waves only
     step_unit<S, kMX>(g, k, B, drive_at(k, n), unit);
+}
+
+__global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel_f64(Grid g, Phys k,
+                                                                        Bufs<double> B,
+                                                                        long long n) {
+    const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
+    if (unit >= g.n_units) return;
+    step_unit<double, false>(g, k, B, drive_at(k, n), unit);
 }
 
 // Step i of a chunk over a batch of channels.  The slot of a unit is found by
@@ -926,9 +967,17 @@ inline int blocks_for(int n, int bs) { return (n + bs - 1) / bs; }
 // ---- plain copy for the bandwidth probe (16-byte vectors, grid-stride) ----
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
                                                    float4* __restrict__ dst, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                     d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 }  // namespace
@@ -956,7 +1005,10 @@ hipError_t launch_step_f32(const Grid& g, const Phys& k, const Bufs<float>& b, b
 }
 hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, int64_t n,
                            hipStream_t s) {
-    return step_impl<double, false>(g, k, b, n, s);
+    if (g.n_units <= 0) return hipSuccess;
+    hipLaunchKernelGGL(step_kernel_f64, dim3(g.n_blocks_pad), dim3(kLanes * kWavesPerBlock), 0, s,
+                       g, k, b, (long long)n);
+    return hipGetLastError();
 }
 
 hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, int step_i,

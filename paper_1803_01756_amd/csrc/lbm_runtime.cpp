@@ -243,8 +243,9 @@ int default_seg_rows(const lbm_params& p, int rows) {
     const int want_units = 2048;
     int segs = std::max(1, (want_units + strips - 1) / strips);
     int sr = (rows + segs - 1) / segs;
-    sr = std::max(sr, std::min(16, rows));
-    return sr;
+    sr = std::max(sr, 14);
+    sr = sr + (6 - (sr + 10) % 6) % 6;  // seg + 10 a multiple of the 6-row unroll
+    return std::min(sr, rows);
 }
 
 void fill_grid(const lbm_params& p, const Layout& L, int seg_rows, Grid& g) {
@@ -725,8 +726,12 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps_per_trial, double* best_ms) {
     if (e == hipSuccess && lb)
         e = hipMemcpyAsync(snap + fb + tb, s->base + s->L.off_lo[f0], lb, hipMemcpyDeviceToDevice,
                            s->stream);
+    // segment heights with seg + 10 (the recomputed halo rows) a multiple of
+    // the kernel's six-row unroll, so full segments need no padding rows
     std::vector<int> cands;
-    for (int c : {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128, 192, 256, 512})
+    for (int c = 2; c <= 128; c += 6)
+        if (c <= s->L.rows) cands.push_back(c);
+    for (int c : {152, 188, 248, 506})
         if (c <= s->L.rows) cands.push_back(c);
     cands.push_back(s->L.rows);
     cands.push_back(default_seg_rows(s->p, s->L.rows));
