@@ -147,6 +147,69 @@ def batch_and_serve(args):
     return batched, served
 
 
+def precision_study():
+    """2048x256 channels with contact angles 60/90/120 degrees (seeds 1-3):
+    FP32 deviation storage against the FP64 build on the GPU, per-field
+    differences at steps 100, 1000 and 20000, and the throughput of both."""
+    import torch
+    from paper_1803_01756_amd import analysis, configs, lbm
+    out = {}
+    for seed, ca in ((1, 60.0), (2, 90.0), (3, 120.0)):
+        p32 = configs.single_gpu_channel(ca, lbm.LBM_FP32_DEV)
+        p64 = configs.single_gpu_channel(ca, lbm.LBM_FP64)
+        rho0 = configs.initial_density(p32, seed=seed)
+        a, b = lbm.Sim(p32, rho0), lbm.Sim(p64, rho0)
+        a.autotune(5)
+        b.autotune(5)
+        n, errs, t32, t64 = 0, {}, 0.0, 0.0
+        for target in (100, 1000, 20000):
+            for s, which in ((a, 32), (b, 64)):
+                s.synchronize()
+                t0 = time.perf_counter()
+                s.step(target - n)
+                s.synchronize()
+                if which == 32:
+                    t32 += time.perf_counter() - t0
+                else:
+                    t64 += time.perf_counter() - t0
+            n = target
+            errs[str(target)] = {k: float("%.3e" % v) for k, v in
+                                 analysis.field_differences(a.moments(), b.moments()).items()}
+        fl = fluid_nodes(p32) * 20000
+        out["%g deg" % ca] = dict(errors_fp32_vs_fp64=errs, fp32_mlups=round(fl / t32 / 1e6, 1),
+                                  fp64_mlups=round(fl / t64 / 1e6, 1))
+        a.close()
+        b.close()
+        log("precision study %g deg: %s" % (ca, errs))
+    return out
+
+
+def large_mass_run(steps=50000, every=1000):
+    """8192x512, mass-exact FP32 storage: FP64 total mass every `every` steps
+    (max relative drift) and the droplets on the plates at the end."""
+    from paper_1803_01756_amd import analysis, configs, lbm
+    p = configs.large_channel(lbm.LBM_FP32_DEV_MASSEXACT)
+    rho0 = configs.initial_density(p, seed=1)
+    s = lbm.Sim(p, rho0)
+    s.autotune(5)
+    m0 = s.reduce()[0]
+    worst = 0.0
+    s.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // every):
+        s.step(every)
+        worst = max(worst, abs(s.reduce()[0] / m0 - 1.0))
+    dt = time.perf_counter() - t0
+    rho = s.moments()[0]
+    drops = analysis.droplets(rho, 0.5 * (s.params.rho_l + s.params.rho_g))
+    s.close()
+    res = dict(steps=steps, max_rel_mass_drift=float("%.3e" % worst),
+               mlups_incl_reductions=round(fluid_nodes(p) * steps / dt / 1e6, 1),
+               droplets=drops)
+    log("large run: %s" % res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +273,10 @@ def main():
         n3 = fluid_nodes(q)
         extra["2048x256_fp32"] = dict(mlups=round(n3 * 4 * k / (m3 * 1e-3) / 1e6, 1),
                                       ms_per_step=round(m3 / (4 * k), 5), seg_rows=s3)
+
+    if not args.no_extra:
+        extra["precision_2048x256"] = precision_study()
+        extra["mass_run_8192x512"] = large_mass_run()
 
     batched = served = None
     if not args.no_batch:

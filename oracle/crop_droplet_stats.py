@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE: runs only the oracle.  Writes
 tests/golden/crop_512x64_droplets.json, against which the GPU run of the same
 crop (same parameters and seed) is compared.  After nucleation the droplet
 positions depend on rounding, so the comparison is on statistics: the number
-of droplets on each plate, their mean spacing and the condensed volume.
+of droplets on each plate, their mean spacing and the condensed volume, and
+the x-averaged profiles of rho, T and u_x across the channel.
 
 Set-up (the 8192 x 512 workload cut to 512 x 64): T_0 = 0.86 Tc, plates at
 0.78 Tc, wall density fraction for a 75 degree contact angle, drive
@@ -91,12 +92,15 @@ def main():
     m0 = s.moments()[0][1:-1].sum()
     for k in range(STEPS // EVERY):
         s.step(EVERY)
-        rho = s.moments()[0]
+        rho, ux, uy, T, _, _ = s.moments()
         st = droplet_stats(rho, thr)
         st["step"] = s.n
         st["mass_rel_drift"] = float(rho[1:-1].sum() / m0 - 1)
-        hist.append(st)
         print(json.dumps(st), "%.0f s" % (time.time() - t0), flush=True)
+        st["rho_profile"] = rho.mean(axis=1).tolist()
+        st["T_profile"] = T.mean(axis=1).tolist()
+        st["ux_profile"] = ux.mean(axis=1).tolist()
+        hist.append(st)
     out = dict(source="oracle/crop_droplet_stats.py (FP64 oracle only)", Nx=NX, Ny=NY, seed=SEED,
                wall_fraction=frac, Tw_over_Tc=0.78, g_osc=2e-6, period=4000.0, history=hist)
     path = os.path.join(ROOT, "tests", "golden", "crop_512x64_droplets.json")

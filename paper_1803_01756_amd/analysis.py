@@ -1,0 +1,65 @@
+"""Post-processing of moment fields: droplets on the plates and per-field
+differences between two runs.  Host-side numpy/scipy; not part of the step."""
+from __future__ import annotations
+
+import numpy as np
+from scipy import ndimage
+
+
+def droplets(rho: np.ndarray, threshold: float):
+    """Droplets touching each plate of a channel field rho[y, x] (plate rows
+    included, periodic in x): connected sets (4-neighbour) of fluid nodes with
+    rho > threshold that reach the first fluid row above the lower plate or
+    below the upper plate.  Returns {"bottom": {count, mean_spacing},
+    "top": {...}, "condensed_nodes": n}."""
+    ny, nx = rho.shape
+    liq = rho > threshold
+    liq[0] = liq[-1] = False
+    lab, n = ndimage.label(liq)
+    # join labels across the periodic x boundary
+    parent = list(range(n + 1))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for y in range(ny):
+        a, b = lab[y, 0], lab[y, nx - 1]
+        if a and b:
+            ra, rb = find(a), find(b)
+            if ra != rb:
+                parent[max(ra, rb)] = min(ra, rb)
+    roots = np.array([find(i) for i in range(n + 1)])
+    lab = roots[lab]
+    out = {}
+    for name, row in (("bottom", 1), ("top", ny - 2)):
+        ids = sorted(set(lab[row][lab[row] > 0].tolist()))
+        centres = []
+        for i in ids:
+            cols = np.nonzero((lab == i).any(axis=0))[0]
+            ang = 2 * np.pi * cols / nx
+            c = (np.arctan2(np.sin(ang).mean(), np.cos(ang).mean()) % (2 * np.pi)) * nx / (2 * np.pi)
+            centres.append(float(c))
+        centres.sort()
+        if len(centres) > 1:
+            spacing = float(np.mean(np.diff(centres + [centres[0] + nx])))
+        else:
+            spacing = float(nx) if centres else 0.0
+        out[name] = dict(count=len(ids), mean_spacing=spacing)
+    out["condensed_nodes"] = int(liq.sum())
+    return out
+
+
+def field_differences(a, b, periodic_y: bool = False):
+    """Per-field differences of run a from run b, each (rho, ux, uy, T):
+    rho and T max relative, u max |du| / max |u_b| (u passes through 0)."""
+    m = np.ones(a[0].shape, dtype=bool)
+    if not periodic_y:
+        m[0] = m[-1] = False
+    e_rho = float(np.max(np.abs(a[0] - b[0])[m] / np.abs(b[0])[m]))
+    e_T = float(np.max(np.abs(a[3] - b[3])[m] / np.abs(b[3])[m]))
+    du = np.hypot(a[1] - b[1], a[2] - b[2])[m]
+    um = float(np.hypot(b[1], b[2])[m].max())
+    return dict(rho=e_rho, u=float(du.max() / um) if um > 0 else float(du.max()), T=e_T)
