@@ -54,24 +54,29 @@ __device__ __forceinline__ double at_xp(double v) {
     return *reinterpret_cast<double*>(&w);
 }
 
+// A row value at x kept as the centre c, the x-sum a = v(x+1) + v(x-1) and
+// the x-difference d = v(x+1) - v(x-1): every nine-point stencil of the
+// step (Eq. 9 force, Eq. 16 gradient, Laplacian and divergence) uses only
+// these three per row, computed once when the row is produced.
 template <class R>
-struct Tri {  // a row value at x, x-1 and x+1
-    R c, m, p;
+struct Tri {
+    R c, a, d;
 };
 template <class R>
 __device__ __forceinline__ Tri<R> tri(R v) {
+    const R m = at_xm(v), p = at_xp(v);
     Tri<R> t;
     t.c = v;
-    t.m = at_xm(v);
-    t.p = at_xp(v);
+    t.a = p + m;
+    t.d = p - m;
     return t;
 }
 template <class R>
 __device__ __forceinline__ Tri<R> tri_const(R v) {
     Tri<R> t;
     t.c = v;
-    t.m = v;
-    t.p = v;
+    t.a = v + v;
+    t.d = (R)0;
     return t;
 }
 
@@ -215,21 +220,23 @@ __device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
 __device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 
-// FP64 reciprocal and square root from the FP32 hardware estimates refined by
-// Newton steps (two for 1/x, two for 1/sqrt(x)): relative error near 1 ulp of
-// FP64 for the positive, normal arguments used here.
+// FP64 reciprocal and square root from the FP32 hardware estimates (relative
+// error ~1e-7) refined by Newton steps, each squaring the error: two steps
+// reach ~1 ulp of FP64 (the FP64 build), one step ~1e-14 relative, far below
+// what FP32 storage resolves (the FP32 builds).
+template <int kSteps>
 __device__ __forceinline__ double rcp_d(double x) {
     double y = (double)__builtin_amdgcn_rcpf((float)x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+#pragma unroll
+    for (int i = 0; i < kSteps; ++i) y = fma(y, fma(-x, y, 1.0), y);
+    return y;
 }
+template <int kSteps>
 __device__ __forceinline__ double sqrt_d(double x) {
     double y = (double)__builtin_amdgcn_rsqf((float)x);
     const double h = 0.5 * x;
-    y = y * fma(-h, y * y, 1.5);
-    y = y * fma(-h, y * y, 1.5);
+#pragma unroll
+    for (int i = 0; i < kSteps; ++i) y = y * fma(-h, y * y, 1.5);
     return x * y;
 }
 
@@ -243,16 +250,17 @@ __device__ __forceinline__ double sqrt_d(double x) {
 // error, not a neighbour difference); the FP64 build takes it in FP64.
 template <bool kF32>
 __device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k) {
+    constexpr int kNewton = kF32 ? 1 : 2;
     const double st = kF32 ? (double)__builtin_amdgcn_sqrtf((float)(T * k.inv_Tc))
-                           : sqrt_d(T * k.inv_Tc);
+                           : sqrt_d<2>(T * k.inv_Tc);
     const double s = 1.0 + k.kappa * (1.0 - st);
     const double br = k.b * rho;
     const double omb = 1.0 - br;
     const double D = 1.0 + br * (2.0 - br);
     const double num = rho * (k.R * T * D - k.a * (s * s) * rho * omb);
-    const double P = num * rcp_d(omb * D);
+    const double P = num * rcp_d<kNewton>(omb * D);
     const double arg = 2.0 * (P - rho * (1.0 / 3.0)) * k.inv_G;
-    return arg > 0.0 ? sqrt_d(arg) : 0.0;
+    return arg > 0.0 ? sqrt_d<kNewton>(arg) : 0.0;
 }
 
 // Eq. 9 + Eq. 14 in one sum: the solid rows carry the effective potential
@@ -260,8 +268,8 @@ __device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k) {
 __device__ __forceinline__ void pair_force(const Tri<double>& pS, const Tri<double>& pC,
                                            const Tri<double>& pN, double negG, double& Fx,
                                            double& Fy) {
-    const double sx = (pC.p - pC.m) * (1.0 / 3.0) + ((pN.p - pN.m) + (pS.p - pS.m)) * (1.0 / 12.0);
-    const double sy = (pN.c - pS.c) * (1.0 / 3.0) + ((pN.p + pN.m) - (pS.p + pS.m)) * (1.0 / 12.0);
+    const double sx = pC.d * (1.0 / 3.0) + (pN.d + pS.d) * (1.0 / 12.0);
+    const double sy = (pN.c - pS.c) * (1.0 / 3.0) + (pN.a - pS.a) * (1.0 / 12.0);
     Fx = negG * pC.c * sx;
     Fy = negG * pC.c * sy;
 }
@@ -331,6 +339,12 @@ __device__ __forceinline__ void collide(R d[9], R drho, R rho, R rinv, R ux, R u
 #pragma unroll
     for (int q = 0; q < 9; ++q)
         a[q] = (m[q] - s[q] * (m[q] - meq[q]) + ((R)1 - (R)0.5 * s[q]) * S[q]) * nrm[q];
+    // conserved moments: m*_0 = m_0 and, since m_eq3 = m_3 + F_x / 2 (the
+    // velocity holds half the force), m*_3 = m_3 + F_x and m*_5 = m_5 + F_y
+    // for any rate; written directly, the rates s_rho and s_j drop out
+    a[0] = drho * nrm[0];
+    a[3] = (m[3] + Fx) * nrm[3];
+    a[5] = (m[5] + Fy) * nrm[5];
     // f* = M^T diag(1/|M_k|^2) m*
     const R b0 = a[0] - a[1] - (R)2 * a[2];
     const R c0 = a[0] + (R)2 * a[1] + a[2];
@@ -356,13 +370,15 @@ __device__ __forceinline__ void collide(R d[9], R drho, R rho, R rinv, R ux, R u
 // (neglected term (T - T_n)^2 / (8 s^3), ~1e-9 relative), which turns the
 // last two terms into -Q1 T - Q0 with Q1 = q1 + q2/(2 s), Q0 = q2 s / 2 and
 // needs one reciprocal square root per row instead of one square root per
-// stage.  The FP64 build keeps the exact sqrt (Q1 = q1, Q0 = 0, q2 kept).
+// stage; with T = T_ref + t (stored deviation) the constant becomes
+// Q0 + Q1 T_ref.  The FP64 build keeps the exact sqrt.
 template <class R>
 struct Coef {
     R ux, uy, q1, q2, q3;
 };
 template <class R>
-__device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, const Phys& k) {
+__device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, R T_ref,
+                                             const Phys& k) {
     const PhysR<R>& pc = pr<R>(k);
     const R br = pc.b * rho;
     const R omb = (R)1 - br;
@@ -380,8 +396,8 @@ __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, co
     if (sizeof(R) == 4) {
         const R rs = (R)__builtin_amdgcn_rsqf((float)Tn);  // 1 / sqrt(T_n)
         const R sn = Tn * rs;
-        q.q1 = q.q1 + q.q2 * (R)0.5 * rs;  // Q1
-        q.q2 = q.q2 * (R)0.5 * sn;         // Q0
+        q.q1 = q.q1 + q.q2 * (R)0.5 * rs;             // Q1
+        q.q2 = q.q2 * (R)0.5 * sn + q.q1 * T_ref;     // Q0 + Q1 T_ref
     }
     return q;
 }
@@ -391,14 +407,14 @@ template <class R>
 __device__ __forceinline__ R heat_rhs(const Tri<R>& tS, const Tri<R>& tC, const Tri<R>& tN,
                                       const Coef<R>& q, R T_ref) {
     const R third = (R)1 / 3, twelfth = (R)1 / 12;
-    const R tx = (tC.p - tC.m) * third + ((tN.p + tS.p) - (tN.m + tS.m)) * twelfth;
-    const R ty = (tN.c - tS.c) * third + ((tN.p + tN.m) - (tS.p + tS.m)) * twelfth;
-    const R ax = (tC.p + tC.m) + (tN.c + tS.c);
-    const R dg = (tN.p + tN.m) + (tS.p + tS.m);
+    const R tx = tC.d * third + (tN.d + tS.d) * twelfth;
+    const R ty = (tN.c - tS.c) * third + (tN.a - tS.a) * twelfth;
+    const R ax = tC.a + (tN.c + tS.c);
+    const R dg = tN.a + tS.a;
     const R lap = ax * ((R)2 / 3) + dg * ((R)1 / 6) - tC.c * ((R)10 / 3);
-    const R Tabs = T_ref + tC.c;
     const R adv_cond = -(q.ux * tx + q.uy * ty) + q.q3 * lap;
-    if (sizeof(R) == 4) return adv_cond - q.q1 * Tabs - q.q2;
+    if (sizeof(R) == 4) return adv_cond - q.q1 * tC.c - q.q2;
+    const R Tabs = T_ref + tC.c;
     return adv_cond - q.q1 * Tabs - q.q2 * sqrt_r(Tabs);
 }
 
@@ -407,8 +423,7 @@ template <class R>
 __device__ __forceinline__ R div_u(const Tri<R>& xS, const Tri<R>& xC, const Tri<R>& xN,
                                    const Tri<R>& yS, const Tri<R>& yC, const Tri<R>& yN) {
     const R third = (R)1 / 3, twelfth = (R)1 / 12;
-    return ((xC.p - xC.m) + (yN.c - yS.c)) * third +
-           (((xN.p - xN.m) + (xS.p - xS.m)) + ((yN.p + yN.m) - (yS.p + yS.m))) * twelfth;
+    return (xC.d + (yN.c - yS.c)) * third + ((xN.d + xS.d) + (yN.a - yS.a)) * twelfth;
 }
 
 template <class S>
@@ -509,38 +524,24 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     // One row iteration; the loop below calls it six times per trip so that
     // the row windows of depth 2, 3 and 6 rotate by renaming registers instead
     // of moving them (a loop holding DPP operations is not unrolled by the
-    // compiler); the depth-4 windows move once per trip.  Padding iterations past the segment only read valid rows and
-    // store nothing; launch shapes with seg_rows + 10 a multiple of 6 need none.
+    // compiler); the depth-4 windows move once per trip.  Launch shapes with
+    // seg_rows + 10 a multiple of 6 need no padding iterations.
     const int kr_end = yb + kHalo;
-    // raw loads of the current row, issued one iteration ahead
-    S curD[9];
-    S curT;
-    float curLo = 0.0f;
-    {
-        const RowK rS = row_info(ya - kHalo, g);
-        const RowK r0 = rS.fluid ? rS : row_info(g.y_first, g);
-        pull_row_buf<S>(rf_in, g, r0, vx, vm, vp, curD);
-        curT = bload(rT_in, vx, (unsigned)r0.sr * rowb, S(0));
-        if (kMX) curLo = bload(rlo_in, x * 4u, (unsigned)r0.sr * (unsigned)g.pitch * 4u, 0.0f);
-    }
     auto row_iteration = [&](const int kr) {
-        // ------------- prefetch: issue the loads of row kr+1 --------------
-        // They complete while this iteration computes; stage A of the next
-        // iteration consumes them.  (Padding iterations past kr_end compute
-        // and load nothing.)
+        // Padding iterations past kr_end load, compute and store nothing.
         const bool live = kr < kr_end;
-        // ------------- stage A: row kr (loaded one iteration ago): rho, j, psi
+        // ------------- stage A: row kr: pull, rho, j, psi -----------------
         const RowK rA = row_info(kr, g);
         Tri<double> psiA;
         R dTA;
         if (rA.fluid && live) {
+            S curD[9];
             pull_row_buf<S>(rf_in, g, rA, vx, vm, vp, curD);
-            curT = bload(rT_in, vx, (unsigned)rA.sr * rowb, S(0));
-            if (kMX) curLo = bload(rlo_in, x * 4u, (unsigned)rA.sr * (unsigned)g.pitch * 4u, 0.0f);
-            const R lo = kMX ? (R)curLo : (R)0;
+            const S rawT = bload(rT_in, vx, (unsigned)rA.sr * rowb, S(0));
+            const R lo = kMX ? (R)bload(rlo_in, x * 4u, (unsigned)rA.sr * (unsigned)g.pitch * 4u, 0.0f)
+                             : (R)0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) dCur[q] = (R)curD[q];
-            const S rawT = curT;
             double drd;
             if (kMX) {
                 drd = (double)dCur[0] + (double)lo;
@@ -601,7 +602,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 // Eq. 8 theta term uses |F_m|^2 / psi^2 of the fluid-fluid force
                 R th = 0;
                 if (!single && psi1.c > 0.0)
-                    th = (R)((Fmx * Fmx + Fmy * Fmy) * rcp_d(psi1.c * psi1.c));
+                    th = (R)((Fmx * Fmx + Fmy * Fmy) * rcp_d<sizeof(S) == 4 ? 1 : 2>(psi1.c * psi1.c));
                 // Eq. 5 with a clamped fraction
                 R fr = (rho - kr_.rho_g) * kr_.inv_drho;
                 fr = fr < (R)0 ? (R)0 : (fr > (R)1 ? (R)1 : fr);
@@ -643,7 +644,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             Tri<R> t1;
             if (rC.fluid && needC) {
                 const R dv = div_u<R>(ux3, ux2, ux1, uy3, uy2, uy1);
-                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, k);
+                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, k);
                 const R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
                 acc2 = h1;
                 t1 = tri<R>(tn2.c + (R)0.5 * h1);
@@ -852,16 +853,15 @@ __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
         if (ys < 0) ys += g.Ny;
         if (yn >= g.Ny) yn -= g.Ny;
     }
-    Tri<double> pS, pC, pN;
-    pS.c = psi[ys * g.Nx + cx];
-    pS.m = psi[ys * g.Nx + xm];
-    pS.p = psi[ys * g.Nx + xp];
-    pC.c = psi[y * g.Nx + cx];
-    pC.m = psi[y * g.Nx + xm];
-    pC.p = psi[y * g.Nx + xp];
-    pN.c = psi[yn * g.Nx + cx];
-    pN.m = psi[yn * g.Nx + xm];
-    pN.p = psi[yn * g.Nx + xp];
+    auto row3 = [&](int yy) {
+        const double m = psi[yy * g.Nx + xm], p = psi[yy * g.Nx + xp];
+        Tri<double> t;
+        t.c = psi[yy * g.Nx + cx];
+        t.a = p + m;
+        t.d = p - m;
+        return t;
+    };
+    const Tri<double> pS = row3(ys), pC = row3(y), pN = row3(yn);
     double Fx = 0.0, Fy = 0.0;
     if (!(k.flags & kSinglePhase))
         pair_force(pS, pC, pN, k.negG, Fx, Fy);
