@@ -1,21 +1,26 @@
-"""Droplet statistics of the cold-wall condensation channel on a 512 x 64
-crop, from the FP64 oracle.
+"""Droplet statistics of the cold-wall condensation channel on crops of the
+8192 x 512 workload, from the FP64 oracle.
 
 TEST INFRASTRUCTURE: runs only the oracle.  Writes
-tests/golden/crop_512x64_droplets.json, against which the GPU run of the same
-crop (same parameters and seed) is compared.  After nucleation the droplet
-positions depend on rounding, so the comparison is on statistics: the number
-of droplets on each plate, their mean spacing and the condensed volume, and
-the x-averaged profiles of rho, T and u_x across the channel.
+tests/golden/crop_<Nx>x<Ny>_droplets.json, against which the GPU run of the
+same crop (same parameters and seed) is compared.  After nucleation the
+droplet positions depend on rounding, so the comparison is on statistics: the
+number of droplets on each plate, their mean spacing and the condensed
+volume, and the x-averaged profiles of rho, T and u_x across the channel.
 
-Set-up (the 8192 x 512 workload cut to 512 x 64): T_0 = 0.86 Tc, plates at
-0.78 Tc, wall density fraction for a 75 degree contact angle, drive
-2e-6 sin(2 pi n / 4000), saturated vapour with +-1 % noise (seed 1),
-50000 steps, statistics every 10000 steps.  A droplet is a connected set
-(4-neighbour, periodic in x) of nodes with rho > (rho_l + rho_g)/2 that
-touches the first fluid row above the lower plate or below the upper plate.
+Set-up: T_0 = 0.86 Tc, plates at 0.78 Tc, wall density fraction for a
+75 degree contact angle, drive 2e-6 sin(2 pi n / 4000), saturated vapour with
++-1 % noise (seed 1), 50000 steps, statistics every 10000 steps.  A droplet
+is a connected set (4-neighbour, periodic in x) of nodes with
+rho > (rho_l + rho_g)/2 that touches the first fluid row above the lower
+plate or below the upper plate.
 
-    python oracle/crop_droplet_stats.py
+Two crops: 512 x 64 (a low channel: it cools through its whole height and
+its vapour stays metastable, no droplets within 50000 steps) and 256 x 512
+(the full height: the cold plates draw vapour from the warm core, the near-
+wall vapour passes the spinodal and droplets form, as on the full channel).
+
+    python oracle/crop_droplet_stats.py [Nx Ny]     (default 512 64)
 """
 import json
 import os
@@ -28,8 +33,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 sys.path.insert(0, ROOT)
 
-NX, NY, STEPS, EVERY, SEED = 512, 64, 50000, 10000, 1
-WALL_FRACTION_75 = None  # filled from the calibration table
+STEPS, EVERY, SEED = 50000, 10000, 1
 
 
 def droplet_stats(rho, thr):
@@ -76,6 +80,7 @@ def droplet_stats(rho, thr):
 
 def main():
     from oracle import oracle as O
+    NX, NY = (int(sys.argv[1]), int(sys.argv[2])) if len(sys.argv) > 2 else (512, 64)
     from paper_1803_01756_amd import inputs
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "contact_angle_table.json")))
     tab = sorted((r["angle"], r["frac"]) for r in gold["table"] if r["angle"] < 180.0)
@@ -103,7 +108,7 @@ def main():
         hist.append(st)
     out = dict(source="oracle/crop_droplet_stats.py (FP64 oracle only)", Nx=NX, Ny=NY, seed=SEED,
                wall_fraction=frac, Tw_over_Tc=0.78, g_osc=2e-6, period=4000.0, history=hist)
-    path = os.path.join(ROOT, "tests", "golden", "crop_512x64_droplets.json")
+    path = os.path.join(ROOT, "tests", "golden", "crop_%dx%d_droplets.json" % (NX, NY))
     json.dump(out, open(path, "w"), indent=1)
     print("wrote", path)
 

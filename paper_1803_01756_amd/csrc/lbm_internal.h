@@ -57,14 +57,15 @@ struct Grid {
     unsigned plane;    // rows * pitch
 };
 
+// Every buffer a step touches lies in one device allocation; the kernel
+// reaches them all through one buffer resource on `base`, by byte offsets.
 template <class S>
 struct Bufs {
-    const S* fin;
-    S* fout;
-    const float* f0lo_in;  // mass-exact low part of the rest population
-    float* f0lo_out;
-    const S* Tin;
-    S* Tout;
+    const char* base;         // the allocation
+    unsigned span;            // bytes from base to the end of the last buffer
+    unsigned fin, fout;       // population buffers: 9 planes of S
+    unsigned lo_in, lo_out;   // mass-exact low parts of the rest population (float)
+    unsigned Tin, Tout;       // temperature planes (Tout unused when T is frozen)
 };
 
 constexpr int kWavesPerBlock = 4;
@@ -83,8 +84,10 @@ hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, 
 struct Slot {
     Grid g;
     Phys k;
-    float* f[2];
-    float* T[2];
+    const char* mem;          // the slot's allocation
+    unsigned span;            // bytes of it the step touches
+    unsigned off_f[2];        // byte offsets of the population buffers
+    unsigned off_T[2];        // and of the temperature planes
     int64_t n0;
     int cur_f, cur_T;
     int steps_left;

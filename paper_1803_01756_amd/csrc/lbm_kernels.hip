@@ -105,6 +105,22 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
 }
 
+// A register copy the compiler cannot fold away: reading a loaded value here
+// places the wait for its load at this point of the program.
+__device__ __forceinline__ float settle(float v) {
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// A uniform value copied into a vector register (kept there by the compiler).
+__device__ __forceinline__ float in_vgpr(float v) {
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ double in_vgpr(double v) { return v; }
+
 // ---- rows -----------------------------------------------------------------
 struct RowK {
     bool fluid;   // stored fluid row
@@ -168,21 +184,22 @@ __device__ __forceinline__ void pull_row(const S* __restrict__ f, const Grid& g,
     d[8] = f[o8];
 }
 
-// The same pull through buffer resources.  Byte offsets: vx, vm, vp are the
-// lane's columns x, x-1, x+1 times sizeof(S); planes and rows are uniform.
+// The same pull through a buffer resource.  vx, vm, vp: byte offsets of the
+// lane's columns x, x-1, x+1; the uniform scalar offset carries the buffer's
+// offset from the resource base (fb) plus the plane and row.
 template <class S>
 __device__ __forceinline__ void pull_row_buf(__amdgpu_buffer_rsrc_t f, const Grid& g,
-                                             const RowK& r, unsigned vx, unsigned vm,
-                                             unsigned vp, S d[9]) {
+                                             const RowK& r, unsigned fb, unsigned vx,
+                                             unsigned vm, unsigned vp, S d[9]) {
     const unsigned P = g.plane * (unsigned)sizeof(S), pitch = (unsigned)g.pitch * sizeof(S);
-    const unsigned rc = (unsigned)r.sr * pitch;
+    const unsigned rc = fb + (unsigned)r.sr * pitch;
     unsigned rdn, rup;
     if (g.periodic_y) {
         int a = r.sr - 1, b = r.sr + 1;
         if (a < 0) a += g.rows;
         if (b >= g.rows) b -= g.rows;
-        rdn = (unsigned)a * pitch;
-        rup = (unsigned)b * pitch;
+        rdn = fb + (unsigned)a * pitch;
+        rup = fb + (unsigned)b * pitch;
     } else {
         rdn = rc - pitch;
         rup = rc + pitch;
@@ -294,8 +311,7 @@ __device__ __forceinline__ const PhysR<double>& pr<double>(const Phys& k) { retu
 // Returns the post-collision deviations in d (overwritten).
 template <class R>
 __device__ __forceinline__ void collide(R d[9], R drho, R rho, R rinv, R ux, R uy, R Fx, R Fy,
-                                        R th, R sv, const Phys& k) {
-    const PhysR<R>& c = pr<R>(k);
+                                        R th, R sv, const PhysR<R>& c) {
     const R s_rho = c.s_rho, s_e = c.s_e, s_z = c.s_z, s_j = c.s_j, s_q = c.s_q;
     const R axis = (d[1] + d[2]) + (d[3] + d[4]);
     const R diag = (d[5] + d[6]) + (d[7] + d[8]);
@@ -378,8 +394,7 @@ struct Coef {
 };
 template <class R>
 __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, R T_ref,
-                                             const Phys& k) {
-    const PhysR<R>& pc = pr<R>(k);
+                                             const PhysR<R>& pc) {
     const R br = pc.b * rho;
     const R omb = (R)1 - br;
     const R D = (R)1 + br * ((R)2 - br);
@@ -478,6 +493,24 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     const bool freezeT = (k.flags & kFreezeT) != 0;
     const bool single = (k.flags & kSinglePhase) != 0;
     const PhysR<R>& kr_ = pr<R>(k);
+    // The collision and heat constants of the FP32 builds live in vector
+    // registers: the scalar registers are short (the loop holds the FP64 EOS
+    // constants, offsets and row state), and a vector operation reads at
+    // most one scalar operand.
+    PhysR<R> cv = kr_;
+    if (sizeof(R) == 4) {
+        cv.s_e = in_vgpr(cv.s_e);
+        cv.s_z = in_vgpr(cv.s_z);
+        cv.s_q = in_vgpr(cv.s_q);
+        cv.c_e = in_vgpr(cv.c_e);
+        cv.c_z = in_vgpr(cv.c_z);
+        cv.b = in_vgpr(cv.b);
+        cv.rkA = in_vgpr(cv.rkA);
+        cv.rkB1 = in_vgpr(cv.rkB1);
+        cv.rkB2 = in_vgpr(cv.rkB2);
+        cv.inv_Cv = in_vgpr(cv.inv_Cv);
+        cv.lambda = in_vgpr(cv.lambda);
+    }
     const R T_ref = kr_.T_ref;
     const R dTw = kr_.dT_wall;
     const R rho_ref = kr_.rho_ref;
@@ -510,16 +543,14 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     cf2 = cf3 = cf4 = cf5 = Coef<R>{0, 0, 0, 0, 0};
     t1a = t1b = t1c = t2a = t2b = t2c = t3a = t3b = t3c = tri_const<R>(dTw);
 
+    // One buffer resource covers every buffer of the step (they share one
+    // allocation); the lane's byte offset is its column, the uniform scalar
+    // offset the buffer, plane and row.
     const unsigned esz = (unsigned)sizeof(S);
-    const unsigned fbytes = 9u * g.plane * esz, tbytes = g.plane * esz;
-    const __amdgpu_buffer_rsrc_t rf_in = make_rsrc(B.fin, fbytes);
-    const __amdgpu_buffer_rsrc_t rf_out = make_rsrc(B.fout, fbytes);
-    const __amdgpu_buffer_rsrc_t rT_in = make_rsrc(B.Tin, tbytes);
-    const __amdgpu_buffer_rsrc_t rT_out = make_rsrc(B.Tout, B.Tout ? tbytes : 0u);
-    const __amdgpu_buffer_rsrc_t rlo_in = make_rsrc(B.f0lo_in, kMX ? g.plane * 4u : 0u);
-    const __amdgpu_buffer_rsrc_t rlo_out = make_rsrc(B.f0lo_out, kMX ? g.plane * 4u : 0u);
-    const unsigned vx = x * esz, vm = xm * esz, vp = xp * esz;
-    const unsigned rowb = (unsigned)g.pitch * esz;
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(B.base, B.span);
+    const unsigned vx = x * esz, vm = xm * esz, vp = xp * esz, vlo = x * 4u;
+    const unsigned rowb = (unsigned)g.pitch * esz, rowb_lo = (unsigned)g.pitch * 4u;
+    const unsigned P = g.plane * esz;
 
     // One row iteration; the loop below calls it six times per trip so that
     // the row windows of depth 2, 3 and 6 rotate by renaming registers instead
@@ -527,21 +558,46 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     // compiler); the depth-4 windows move once per trip.  Launch shapes with
     // seg_rows + 10 a multiple of 6 need no padding iterations.
     const int kr_end = yb + kHalo;
+    // FP32 builds load row kr+1 at the top of iteration kr and move it into
+    // the registers stage A reads (cur) just before the last stage, so the
+    // loads overlap most of an iteration and the wait for them falls before
+    // the last store of the iteration rather than after it (one counter
+    // tracks both).  Every iteration loads: a row that is not a stored fluid
+    // row of the segment's range reads the first stored row instead (values
+    // never used).  The FP64 build (twice the registers per value) loads each
+    // row in stage A of its own iteration.
+    constexpr bool kAhead = sizeof(S) == 4;
+    struct RawRow {
+        S d[9];
+        S T;
+        float lo;
+    };
+    RawRow raw, cur;
+    auto issue_loads = [&](const int y, RawRow& dst) {
+        const RowK rL = row_info(y, g);
+        const RowK rS = (rL.fluid && y < kr_end) ? rL : row_info(g.y_first, g);
+        pull_row_buf<S>(rb, g, rS, B.fin, vx, vm, vp, dst.d);
+        dst.T = bload(rb, vx, B.Tin + (unsigned)rS.sr * rowb, S(0));
+        dst.lo = kMX ? bload(rb, vlo, B.lo_in + (unsigned)rS.sr * rowb_lo, 0.0f) : 0.0f;
+    };
+    if (kAhead) {
+        issue_loads(ya - kHalo, raw);
+        cur = raw;
+    }
     auto row_iteration = [&](const int kr) {
-        // Padding iterations past kr_end load, compute and store nothing.
+        // Padding iterations past kr_end compute and store nothing.
         const bool live = kr < kr_end;
+        if (kAhead) issue_loads(kr + 1, raw);
         // ------------- stage A: row kr: pull, rho, j, psi -----------------
         const RowK rA = row_info(kr, g);
         Tri<double> psiA;
         R dTA;
         if (rA.fluid && live) {
-            S curD[9];
-            pull_row_buf<S>(rf_in, g, rA, vx, vm, vp, curD);
-            const S rawT = bload(rT_in, vx, (unsigned)rA.sr * rowb, S(0));
-            const R lo = kMX ? (R)bload(rlo_in, x * 4u, (unsigned)rA.sr * (unsigned)g.pitch * 4u, 0.0f)
-                             : (R)0;
+            if (!kAhead) issue_loads(kr, cur);
+            const S rawT = cur.T;
+            const R lo = kMX ? (R)cur.lo : (R)0;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) dCur[q] = (R)curD[q];
+            for (int q = 0; q < 9; ++q) dCur[q] = (R)cur.d[q];
             double drd;
             if (kMX) {
                 drd = (double)dCur[0] + (double)lo;
@@ -610,10 +666,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 R dn[9];
 #pragma unroll
                 for (int q = 0; q < 9; ++q) dn[q] = dPrv[q];
-                collide<R>(dn, drPrv, rho, rinv, ux, uy, Fx, Fy, th, sv, k);
+                collide<R>(dn, drPrv, rho, rinv, ux, uy, Fx, Fy, th, sv, cv);
                 if (own_lane) {
-                    const unsigned so = (unsigned)rB.sr * rowb;
-                    const unsigned P = g.plane * esz;
+                    const unsigned so = B.fout + (unsigned)rB.sr * rowb;
                     if (kMX) {
                         // rest population takes whatever keeps sum_i d_i equal to
                         // the pre-collision deviation density (FP64), as (hi, lo)
@@ -621,14 +676,14 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
 #pragma unroll
                         for (int q = 1; q < 9; ++q) rest -= (double)(S)dn[q];
                         const float hi = (float)rest;
-                        bstore((S)hi, rf_out, vx, so);
-                        bstore((float)(rest - (double)hi), rlo_out, x * 4u,
-                               (unsigned)rB.sr * (unsigned)g.pitch * 4u);
+                        bstore((S)hi, rb, vx, so);
+                        bstore((float)(rest - (double)hi), rb, vlo,
+                               B.lo_out + (unsigned)rB.sr * rowb_lo);
                     } else {
-                        bstore((S)dn[0], rf_out, vx, so);
+                        bstore((S)dn[0], rb, vx, so);
                     }
 #pragma unroll
-                    for (int q = 1; q < 9; ++q) bstore((S)dn[q], rf_out, vx, q * P + so);
+                    for (int q = 1; q < 9; ++q) bstore((S)dn[q], rb, vx, q * P + so);
                 }
             }
         } else {
@@ -644,7 +699,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             Tri<R> t1;
             if (rC.fluid && needC) {
                 const R dv = div_u<R>(ux3, ux2, ux1, uy3, uy2, uy1);
-                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, k);
+                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, cv);
                 const R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
                 acc2 = h1;
                 t1 = tri<R>(tn2.c + (R)0.5 * h1);
@@ -676,11 +731,19 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             }
             t3a = t3;
             // ------------- stage F: h4 and T(n+1) on row kr-5 -------------
+        }
+        if (kAhead) {  // row kr+1 into the registers of the next iteration
+#pragma unroll
+            for (int q = 0; q < 9; ++q) cur.d[q] = settle(raw.d[q]);
+            cur.T = settle(raw.T);
+            if (kMX) cur.lo = settle(raw.lo);
+        }
+        if (!freezeT) {
             const RowK rF = row_info(kr - 5, g);
             if (rF.fluid && kr - 5 >= ya && kr - 5 < yb) {
                 const R h4 = heat_rhs<R>(t3c, t3b, t3a, cf5, T_ref);
                 const R tnew = tn5 + (acc5 + h4) * ((R)1 / 6);
-                if (own_lane) bstore((S)tnew, rT_out, vx, (unsigned)rF.sr * rowb);
+                if (own_lane) bstore((S)tnew, rb, vx, B.Tout + (unsigned)rF.sr * rowb);
             }
         }
 
@@ -769,18 +832,18 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_batched_kernel(
     const Grid g = sl.g;
     const Phys k = sl.k;
     Bufs<float> B;
+    B.base = sl.mem;
+    B.span = sl.span;
     const int a = (sl.cur_f + step_i) & 1;
-    B.fin = a ? sl.f[1] : sl.f[0];
-    B.fout = a ? sl.f[0] : sl.f[1];
-    B.f0lo_in = nullptr;
-    B.f0lo_out = nullptr;
+    B.fin = sl.off_f[a];
+    B.fout = sl.off_f[a ^ 1];
+    B.lo_in = B.lo_out = 0;
     if (sl.k.flags & kFreezeT) {
-        B.Tin = sl.cur_T ? sl.T[1] : sl.T[0];
-        B.Tout = nullptr;
+        B.Tin = B.Tout = sl.off_T[sl.cur_T];
     } else {
         const int t = (sl.cur_T + step_i) & 1;
-        B.Tin = t ? sl.T[1] : sl.T[0];
-        B.Tout = t ? sl.T[0] : sl.T[1];
+        B.Tin = sl.off_T[t];
+        B.Tout = sl.off_T[t ^ 1];
     }
     step_unit<float, false>(g, k, B, drive_at(k, sl.n0 + step_i), unit - sl.unit_begin);
 }
@@ -964,28 +1027,27 @@ __global__ __launch_bounds__(64) void reduce_pass2(const double* __restrict__ pa
 
 inline int blocks_for(int n, int bs) { return (n + bs - 1) / bs; }
 
-// ---- plain copy for the bandwidth probe (16-byte vectors, grid-stride) ----
-__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
-                                                   float4* __restrict__ dst, size_t n) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
-                     d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
-    }
-    for (; i < n; i += stride) dst[i] = src[i];
+// ---- plain copy for the bandwidth probe -----------------------------------
+// One 16-byte vector per thread, streaming (non-temporal) loads and stores:
+// the fastest of the plain copy forms measured on MI355X (grid-stride loops
+// with 2k-128k blocks, unrolled by 1 and 4, with and without the
+// non-temporal hint), so the probe is a fair ceiling for the step kernel.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_kernel(const f32x4* __restrict__ src,
+                                                   f32x4* __restrict__ dst, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
 }  // namespace
 
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
     const size_t n = bytes / 16;
-    hipLaunchKernelGGL(copy_kernel, dim3(256 * 32), dim3(256), 0, s,
-                       static_cast<const float4*>(src), static_cast<float4*>(dst), n);
+    const size_t blocks = (n + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const f32x4*>(src), static_cast<f32x4*>(dst), n);
     return hipGetLastError();
 }
 

@@ -289,10 +289,12 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
         lbmk::Slot& t = tab[j];
         t.g = s.g;
         t.k = s.k;
-        t.f[0] = s.f[0];
-        t.f[1] = s.f[1];
-        t.T[0] = s.T[0];
-        t.T[1] = s.T[1];
+        t.mem = s.mem;
+        for (int q = 0; q < 2; ++q) {
+            t.off_f[q] = (unsigned)(reinterpret_cast<char*>(s.f[q]) - s.mem);
+            t.off_T[q] = (unsigned)(reinterpret_cast<char*>(s.T[q]) - s.mem);
+        }
+        t.span = t.off_T[1] + (unsigned)(s.L.plane * 4);
         t.n0 = s.n;
         t.cur_f = s.cur_f;
         t.cur_T = s.cur_T;

@@ -146,7 +146,7 @@ bool make_layout(const lbm_params& p, Layout* L) {
     L->rows = per ? p.Ny : p.Ny - 2;
     L->plane = (size_t)L->pitch * L->rows;
     L->esz = p.precision == LBM_FP64 ? 8 : 4;
-    if (9 * L->plane >= (size_t)1 << 32) return false;  // 32-bit element offsets
+
     const size_t cells = (size_t)p.Nx * p.Ny;
     size_t o = 0;
     for (int b = 0; b < 2; ++b) {
@@ -161,6 +161,8 @@ bool make_layout(const lbm_params& p, Layout* L) {
         L->off_T[b] = o;
         o = align_up(o + L->plane * L->esz);
     }
+    // the step reaches its buffers by 32-bit byte offsets from the base
+    if (o >= ((size_t)1 << 32) - kAlign) return false;
     L->off_mom = o;
     o = align_up(o + 4 * cells * sizeof(double));
     L->off_scr = o;
@@ -192,7 +194,7 @@ lbm_status validate(const lbm_params& p) {
     if (!(p.C_v > 0.0) || p.lambda < 0.0) return fail(LBM_EINVAL, "C_v > 0, lambda >= 0 needed");
     if (!(p.rho_ref > 0.0)) return fail(LBM_EINVAL, "rho_ref must be positive");
     Layout L;
-    if (!make_layout(p, &L)) return fail(LBM_EINVAL, "grid too large for 32-bit offsets");
+    if (!make_layout(p, &L)) return fail(LBM_EINVAL, "grid too large: the step buffers must stay below 4 GiB");
     return LBM_OK;
 }
 
@@ -348,13 +350,16 @@ hipError_t enqueue_step(lbm_sim* s) {
     const int fa = s->fcur, fb = 1 - s->fcur;
     const int ta = s->tcur, tb = (s->p.flags & LBM_FREEZE_T) ? s->tcur : 1 - s->tcur;
     hipError_t e;
+    const unsigned span = (unsigned)(s->L.off_T[1] + s->L.plane * s->L.esz);
+    const auto off = [](size_t o) { return (unsigned)o; };
     if (s->p.precision == LBM_FP64) {
-        lbmk::Bufs<double> b{s->f<double>(fa), s->f<double>(fb), nullptr, nullptr,
-                             s->T<double>(ta), s->T<double>(tb)};
+        lbmk::Bufs<double> b{s->base, span, off(s->L.off_f[fa]), off(s->L.off_f[fb]), 0u, 0u,
+                             off(s->L.off_T[ta]), off(s->L.off_T[tb])};
         e = lbmk::launch_step_f64(s->g, s->k, b, s->n, s->stream);
     } else {
-        lbmk::Bufs<float> b{s->f<float>(fa), s->f<float>(fb), s->lo(fa), s->lo(fb),
-                            s->T<float>(ta), s->T<float>(tb)};
+        lbmk::Bufs<float> b{s->base, span, off(s->L.off_f[fa]), off(s->L.off_f[fb]),
+                            off(s->L.off_lo[fa]), off(s->L.off_lo[fb]),
+                            off(s->L.off_T[ta]), off(s->L.off_T[tb])};
         e = lbmk::launch_step_f32(s->g, s->k, b, s->p.precision == LBM_FP32_DEV_MASSEXACT, s->n,
                                   s->stream);
     }
