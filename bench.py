@@ -210,6 +210,48 @@ def large_mass_run(steps=50000, every=1000):
     return res
 
 
+def d2_law_study(N=200, D=60.0, max_steps=320000, every=4000):
+    """Sec. 3.1 droplet evaporation on the paper's 200 x 200 box (D = 60,
+    frame reservoir at T_c, lambda = 1/3 and 2/3), FP32 deviations: the D^2
+    slope K fitted where (D/D0)^2 falls from 0.8 to 0.2, its R^2, the ratio
+    of the two slopes, and the oracle's slopes for the same set-up when its
+    record (tests/golden/d2_law_200.json) is present."""
+    import numpy as np
+    from paper_1803_01756_amd import analysis, configs, lbm
+    gold_path = os.path.join(ROOT, "tests", "golden", "d2_law_%d.json" % N)
+    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+    out = {}
+    for lam in (1.0 / 3.0, 2.0 / 3.0):
+        p = configs.d2_box(lam, lbm.LBM_FP32_DEV, N=N)
+        s = lbm.Sim(p, configs.droplet_density(p, D))
+        s.autotune(3)
+        t, d = [0], [analysis.equivalent_diameter(s.moments()[0], p.rho_l, p.rho_g)]
+        s.synchronize()
+        t0 = time.perf_counter()
+        while s.n < max_steps and d[-1] > 0.3 * d[0]:
+            s.step(every)
+            t.append(s.n)
+            d.append(analysis.equivalent_diameter(s.moments()[0], p.rho_l, p.rho_g))
+        dt = time.perf_counter() - t0
+        s.close()
+        ta, d2 = np.array(t, float), (np.array(d) / d[0]) ** 2
+        sel = (d2 > 0.2) & (d2 < 0.8)
+        K, r2 = analysis.d2_fit(ta[sel], d2[sel]) if sel.sum() >= 3 else (None, None)
+        rec = dict(K=K, R2=None if r2 is None else round(r2, 5), steps=int(s.n),
+                   mlups_incl_readout=round(N * N * s.n / dt / 1e6, 1))
+        if gold:
+            ref = [c for c in gold["cases"] if abs(c["lam"] - lam) < 1e-12][0]
+            rec["oracle_K"] = ref["K"]
+            if K and ref["K"]:
+                rec["K_rel_diff"] = float("%.3e" % (K / ref["K"] - 1))
+        out["lambda=%.4f" % lam] = rec
+        log("d2 law lambda %.4f: %s" % (lam, rec))
+    ks = [v["K"] for v in out.values()]
+    if all(ks):
+        out["K_ratio_2_over_1"] = round(ks[1] / ks[0], 4)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +319,7 @@ def main():
     if not args.no_extra:
         extra["precision_2048x256"] = precision_study()
         extra["mass_run_8192x512"] = large_mass_run()
+        extra["d2_law_200x200"] = d2_law_study()
 
     batched = served = None
     if not args.no_batch:

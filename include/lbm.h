@@ -62,7 +62,21 @@ enum {
 enum {
     LBM_FREEZE_T = 1u,     /* isothermal: skip the temperature update           */
     LBM_SINGLE_PHASE = 2u, /* F_m = 0 and no theta term (ideal-gas flow checks) */
-    LBM_PERIODIC_Y = 4u    /* no plates: periodic in y as well                  */
+    LBM_PERIODIC_Y = 4u,   /* no plates: periodic in y as well                  */
+    LBM_FRAME_T = 8u,      /* Sec. 3.1 (droplet in surroundings at a set
+                              temperature): the outermost columns, and with
+                              LBM_PERIODIC_Y the outermost rows, form a frame
+                              whose temperature is held at T_w in every RK
+                              stage                                          */
+    LBM_FRAME_RHO = 16u,   /* the same frame is an open reservoir at rest:
+                              rho = rho_frame and u = 0 there, and its
+                              post-collision populations are the rest
+                              equilibrium of rho_frame (mass is then not
+                              conserved: vapour leaves or enters)            */
+    LBM_EOS_CS = 32u       /* Carnahan-Starling EOS in place of Eq. 11:
+                              P = rho R T (1 + e + e^2 - e^3) / (1 - e)^3
+                              - a rho^2, e = b rho / 4 (usual constants
+                              a = 1, b = 4, R = 1); omega is then unused   */
 };
 
 /* Parameters, named as in the paper.  lbm_params_default() fills the paper's
@@ -85,8 +99,10 @@ typedef struct {
     double rho_v;           /* Eq. 15 reference vapour density; < 0: Maxwell gas  */
     double rho_ref;         /* density of the stored deviations; <= 0: rho_v (or
                                the Maxwell gas density when rho_v is 0)          */
+    double rho_frame;       /* LBM_FRAME_RHO reservoir density (> 0 required)   */
     int32_t precision;      /* LBM_FP32_DEV, LBM_FP64 or LBM_FP32_DEV_MASSEXACT   */
-    uint32_t flags;         /* LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y   */
+    uint32_t flags;         /* LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y |
+                               LBM_FRAME_T | LBM_FRAME_RHO                       */
 } lbm_params;
 
 /* Fill *p with the defaults: Nx = 128, Ny = 32, a = 3/49, b = 2/21, R = 1,
@@ -109,6 +125,8 @@ lbm_status lbm_params_resolve(lbm_params* p);
  * coexistence densities at temperature T (equal pressure and chemical
  * potential).  Host FP64. */
 lbm_status lbm_eos_critical(double a, double b, double R, double* rho_c, double* T_c);
+/* The critical point of the Carnahan-Starling EOS (LBM_EOS_CS). */
+lbm_status lbm_eos_critical_cs(double a, double b, double R, double* rho_c, double* T_c);
 lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_g, double* rho_l,
                                double* p_sat);
 
@@ -116,6 +134,15 @@ lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_g, dou
  * 0) for the EOS constants and G of *p (T_c <= 0: derived).  Host FP64; used
  * e.g. to turn a virtual wall density into psi_w. */
 lbm_status lbm_eos_pressure(const lbm_params* p, double rho, double T, double* P, double* psi);
+
+/* Latent heat of Eq. 19 at T < T_c (per unit mass, lattice units): the
+ * internal-energy difference of the coexisting phases integrated over the
+ * EOS, [a phi(T) - T a dphi/dT] / (2 sqrt2 b) times the difference of
+ * ln[(1 + (1+sqrt2) b rho) / (1 + (1-sqrt2) b rho)] between liquid and vapour,
+ * plus p_s (1/rho_g - 1/rho_l); the paper's c_alpha and c_a are the PR kappa.
+ * The Jacob number of Eq. 20 is C_v (T_sat - T_w) / h_fg(T_sat).  Host FP64.
+ * LBM_EINVAL if T is not below T_c or no coexistence is found. */
+lbm_status lbm_eos_latent_heat(const lbm_params* p, double T, double* h_fg);
 
 /* Device bytes a simulation with these parameters needs (two population
  * buffers, two temperature buffers, moment scratch), for callers that

@@ -43,6 +43,14 @@
  *    half-way bounce-back.
  *  - Plates are the solid rows y = 0 and y = Ny-1; the flag PERIODIC_Y
  *    removes them.
+ *  - Sec. 3.1 (D^2 law): the droplet sits in surroundings at T_c.  Reading:
+ *    the outermost columns (and, in a periodic box, the outermost rows) form
+ *    a frame.  With FRAME_T its temperature is held at T_w in every stage,
+ *    like the solid nodes of the plates; with FRAME_RHO it is also an open
+ *    reservoir at rest: rho = rho_frame and u = 0 there, and its
+ *    post-collision populations are the rest equilibrium of rho_frame, so
+ *    evaporated vapour can leave the box (a closed box only heats up and
+ *    compresses its vapour).
  */
 #define _USE_MATH_DEFINES
 #include <math.h>
@@ -54,6 +62,11 @@
 #define ORC_FREEZE_T 1u     /* skip the temperature update (isothermal)     */
 #define ORC_SINGLE_PHASE 2u /* F_m = 0 and theta term = 0 (ideal gas flow)  */
 #define ORC_PERIODIC_Y 4u   /* no plates: periodic in y as well             */
+#define ORC_FRAME_T 8u      /* T held at T_w on the outermost columns (and  */
+                            /* rows when periodic in y)                     */
+#define ORC_FRAME_RHO 16u   /* the same frame is a reservoir at rest with   */
+                            /* density rho_frame                            */
+#define ORC_EOS_CS 32u      /* Carnahan-Starling EOS in place of Eq. 11     */
 
 typedef struct {
     int32_t Nx, Ny;
@@ -66,6 +79,7 @@ typedef struct {
     double T0, Tw;                /* initial fluid / wall temperature */
     double g_osc, period;         /* oscillating drive along +x */
     double gx, gy, rho_v;         /* Eq. 15 */
+    double rho_frame;             /* FRAME_RHO reservoir density */
     uint32_t flags;
     int32_t pad_;
 } orc_params;
@@ -131,20 +145,36 @@ double orc_phi(const orc_params* p, double T) {
     double s = 1.0 + kappa_of(p->omega) * (1.0 - sqrt(T / p->Tc));
     return s * s;
 }
+/* Carnahan-Starling alternative (the EOS the problem statement falls back to
+ * when the paper's is not used), with eta = b rho / 4:
+ *   P = rho R T (1 + eta + eta^2 - eta^3) / (1 - eta)^3 - a rho^2          */
+static double cs_z(double eta) {
+    double o = 1.0 - eta;
+    return (1.0 + eta + eta * eta - eta * eta * eta) / (o * o * o);
+}
 /* P_EOS(rho, T) = rho R T / (1 - b rho) - a phi(T) rho^2 / (1 + 2 b rho - b^2 rho^2) */
 double orc_peos(const orc_params* p, double rho, double T) {
     double b = p->b;
+    if (p->flags & ORC_EOS_CS) return rho * p->R * T * cs_z(0.25 * b * rho) - p->a * rho * rho;
     return rho * p->R * T / (1.0 - b * rho) -
            p->a * orc_phi(p, T) * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
 }
-/* (dP/drho)_T, derived by hand from Eq. 11 */
+/* (dP/drho)_T, derived by hand from Eq. 11 (and from the CS form:
+ * d(eta Z)/d eta = (1 + 4 eta + 4 eta^2 - 4 eta^3 + eta^4) / (1 - eta)^4) */
 double orc_dpdrho(const orc_params* p, double rho, double T) {
     double b = p->b, D = 1.0 + 2.0 * b * rho - b * b * rho * rho;
+    if (p->flags & ORC_EOS_CS) {
+        double e = 0.25 * b * rho, o = 1.0 - e;
+        return p->R * T * (1.0 + 4.0 * e + 4.0 * e * e - 4.0 * e * e * e + e * e * e * e) /
+                   (o * o * o * o) - 2.0 * p->a * rho;
+    }
     return p->R * T / ((1.0 - b * rho) * (1.0 - b * rho)) -
            2.0 * p->a * orc_phi(p, T) * rho * (1.0 + b * rho) / (D * D);
 }
-/* (dP/dT)_rho: phi'(T) = -kappa [1 + kappa (1 - sqrt(T/Tc))] / sqrt(T Tc) */
+/* (dP/dT)_rho: phi'(T) = -kappa [1 + kappa (1 - sqrt(T/Tc))] / sqrt(T Tc);
+ * CS: rho R Z(eta) */
 double orc_dpdT(const orc_params* p, double rho, double T) {
+    if (p->flags & ORC_EOS_CS) return rho * p->R * cs_z(0.25 * p->b * rho);
     double b = p->b, k = kappa_of(p->omega);
     double D = 1.0 + 2.0 * b * rho - b * b * rho * rho;
     double dphi = -k * (1.0 + k * (1.0 - sqrt(T / p->Tc))) / sqrt(T * p->Tc);
@@ -176,6 +206,25 @@ void orc_critical(double a, double b, double R, double* rho_c, double* T_c) {
     }
     *rho_c = 0.5 * (lo + hi);
     *T_c = tsp(a, b, R, *rho_c);
+}
+/* the same for the CS EOS: T_sp = 2 a rho (1 - eta)^4 / (R (1 + 4 eta + 4 eta^2
+ * - 4 eta^3 + eta^4)) on 0 < eta < 1 */
+static double tsp_cs(double a, double b, double R, double rho) {
+    double e = 0.25 * b * rho, o = 1.0 - e;
+    return 2.0 * a * rho * o * o * o * o /
+           (R * (1.0 + 4.0 * e + 4.0 * e * e - 4.0 * e * e * e + e * e * e * e));
+}
+void orc_critical_cs(double a, double b, double R, double* rho_c, double* T_c) {
+    double lo = 1e-9, hi = 4.0 / b - 1e-9;
+    const double gr = 0.5 * (sqrt(5.0) - 1.0);
+    double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+    double f1 = tsp_cs(a, b, R, x1), f2 = tsp_cs(a, b, R, x2);
+    for (int it = 0; it < 400 && hi - lo > 1e-15 * hi; ++it) {
+        if (f1 < f2) { lo = x1; x1 = x2; f1 = f2; x2 = lo + gr * (hi - lo); f2 = tsp_cs(a, b, R, x2); }
+        else { hi = x2; x2 = x1; f2 = f1; x1 = hi - gr * (hi - lo); f1 = tsp_cs(a, b, R, x1); }
+    }
+    *rho_c = 0.5 * (lo + hi);
+    *T_c = tsp_cs(a, b, R, *rho_c);
 }
 
 /* bisection for a root of g on [lo, hi] with a sign change */
@@ -213,7 +262,7 @@ static double area(const orc_params* p, double T, double ps, double rg, double r
 /* Maxwell equal-area coexistence at temperature T < Tc.  Returns 0 on
  * success, -1 if T is not below the critical temperature. */
 int orc_maxwell(const orc_params* p, double T, double* rho_g, double* rho_l, double* p_sat) {
-    double bmax = 1.0 / p->b;
+    double bmax = (p->flags & ORC_EOS_CS) ? 4.0 / p->b : 1.0 / p->b; /* packing limit */
     /* minimum of dP/drho locates the middle of the unstable branch */
     double lo = 1e-9, hi = bmax * (1.0 - 1e-9);
     const double gr = 0.5 * (sqrt(5.0) - 1.0);
@@ -262,6 +311,32 @@ static void eq_moments(double rho, double jx, double jy, double meq[9]) {
     meq[6] = -jy;
     meq[7] = (jx * jx - jy * jy) / rho;
     meq[8] = jx * jy / rho;
+}
+
+/* Eq. 19: latent heat at T < Tc from the coexistence densities, as printed:
+ *   h_fg = [a phi(T) + a kappa sqrt(T/Tc) (1 + kappa (1 - sqrt(T/Tc)))]
+ *          / (2 sqrt(2) b) * ln|(b rho_g - 1 - sqrt2)(b rho_l - 1 + sqrt2)
+ *                              / ((b rho_g - 1 + sqrt2)(b rho_l - 1 - sqrt2))|
+ *          + p_s (1/rho_g - 1/rho_l).
+ * The two coefficients the paper calls c_alpha and c_a are read as the PR
+ * kappa(omega) of Eq. 11: the bracket is then a - T da/dT, and the formula
+ * is the internal-energy difference of the two phases integrated over the
+ * EOS (the logarithm is the antiderivative of 1/(1 + 2 b rho - b^2 rho^2))
+ * plus p_s times the volume change.  Returns 0, or -1 above Tc. */
+int orc_latent_heat(const orc_params* p, double T, double* h_fg) {
+    double rg, rl, ps;
+    if (orc_maxwell(p, T, &rg, &rl, &ps) != 0) return -1;
+    if (p->flags & ORC_EOS_CS) { /* attraction a rho^2 independent of T: du = -a drho */
+        *h_fg = p->a * (rl - rg) + ps * (1.0 / rg - 1.0 / rl);
+        return 0;
+    }
+    const double k = kappa_of(p->omega), st = sqrt(T / p->Tc), r2 = sqrt(2.0), b = p->b;
+    const double coef = (p->a * orc_phi(p, T) + p->a * k * st * (1.0 + k * (1.0 - st))) /
+                        (2.0 * r2 * b);
+    const double arg = ((b * rg - 1.0 - r2) * (b * rl - 1.0 + r2)) /
+                       ((b * rg - 1.0 + r2) * (b * rl - 1.0 - r2));
+    *h_fg = coef * log(fabs(arg)) + ps * (1.0 / rg - 1.0 / rl);
+    return 0;
 }
 
 /* Collision of one node, Eq. 7 then f* = M^-1 m*:
@@ -329,6 +404,21 @@ static int is_solid(const orc_params* p, int y) {
     return y == 0 || y == p->Ny - 1;
 }
 static int wrapx(const orc_params* p, int x) { return (x % p->Nx + p->Nx) % p->Nx; }
+/* the frame of the box: outermost columns, and outermost rows when periodic
+ * in y (Sec. 3.1 reading in the header) */
+static int on_frame(const orc_params* p, int x, int y) {
+    if (x == 0 || x == p->Nx - 1) return 1;
+    return (p->flags & ORC_PERIODIC_Y) && (y == 0 || y == p->Ny - 1);
+}
+/* nodes whose temperature is a boundary value: the plates and a FRAME_T frame */
+static int t_held(const orc_params* p, int x, int y) {
+    if (is_solid(p, y)) return 1;
+    return (p->flags & ORC_FRAME_T) && on_frame(p, x, y);
+}
+/* reservoir nodes of a FRAME_RHO frame */
+static int reservoir(const orc_params* p, int x, int y) {
+    return (p->flags & ORC_FRAME_RHO) && !is_solid(p, y) && on_frame(p, x, y);
+}
 static int wrapy(const orc_params* p, int y) {
     if (p->flags & ORC_PERIODIC_Y) return (y % p->Ny + p->Ny) % p->Ny;
     return y; /* fluid rows 1..Ny-2 never reach past rows 0 and Ny-1 */
@@ -378,7 +468,7 @@ void orc_sim_init(orc_sim* s, const double* rho0, double rho_uniform) {
                 feq[i] = v;
             }
             for (int i = 0; i < 9; ++i) s->f[FIDX(p, i, x, y)] = is_solid(p, y) ? 0.0 : feq[i];
-            s->T[IDX(p, x, y)] = is_solid(p, y) ? p->Tw : p->T0;
+            s->T[IDX(p, x, y)] = t_held(p, x, y) ? p->Tw : p->T0;
         }
 }
 void orc_sim_set_f(orc_sim* s, const double* f) {
@@ -405,6 +495,7 @@ static void macroscopic(orc_sim* s) {
             if (is_solid(p, y)) { s->rho[c] = 0.0; s->psi[c] = p->psiw; continue; }
             double r = 0.0;
             for (int i = 0; i < 9; ++i) r += s->f[FIDX(p, i, x, y)];
+            if (reservoir(p, x, y)) r = p->rho_frame;
             s->rho[c] = r;
             double arg = 2.0 * (orc_peos(p, r, s->T[c]) - r / 3.0) / p->G;
             if (!(arg > 0.0)) s->psi_clamps++;
@@ -454,6 +545,7 @@ static void macroscopic(orc_sim* s) {
             }
             s->ux[c] = (jx + 0.5 * s->Fx[c]) / r;
             s->uy[c] = (jy + 0.5 * s->Fy[c]) / r;
+            if (reservoir(p, x, y)) s->ux[c] = s->uy[c] = 0.0;
         }
 }
 
@@ -511,6 +603,15 @@ static void step_once(orc_sim* s) {
             for (int i = 0; i < 9; ++i) f[i] = s->f[FIDX(p, i, x, y)];
             orc_collide_node(p, f, s->rho[c], s->ux[c], s->uy[c], s->Fx[c], s->Fy[c], s->Fmx[c],
                              s->Fmy[c], s->psi[c], tau_visc(p, s->rho[c]), fo);
+            if (reservoir(p, x, y)) { /* rest equilibrium of the reservoir density */
+                double meq[9];
+                eq_moments(p->rho_frame, 0.0, 0.0, meq);
+                for (int i = 0; i < 9; ++i) {
+                    double v = 0.0;
+                    for (int k = 0; k < 9; ++k) v += MINV[i][k] * meq[k];
+                    fo[i] = v;
+                }
+            }
             for (int i = 0; i < 9; ++i) s->fpost[FIDX(p, i, x, y)] = fo[i];
         }
     /* S7: classical RK4 for T (Eqs. 16-18) with rho(n), u(n) frozen */
@@ -524,20 +625,20 @@ static void step_once(orc_sim* s) {
             for (int y = 0; y < Ny; ++y)
                 for (int x = 0; x < Nx; ++x) {
                     size_t c = IDX(p, x, y);
-                    if (is_solid(p, y)) continue;
+                    if (t_held(p, x, y)) continue;
                     s->acc[c] += wts[st] * s->h[c];
                 }
             for (int y = 0; y < Ny; ++y)
                 for (int x = 0; x < Nx; ++x) {
                     size_t c = IDX(p, x, y);
-                    if (is_solid(p, y)) continue;
+                    if (t_held(p, x, y)) continue;
                     s->Ts[c] = s->T[c] + cst[st] * s->h[c];
                 }
         }
         for (int y = 0; y < Ny; ++y)
             for (int x = 0; x < Nx; ++x) {
                 size_t c = IDX(p, x, y);
-                if (!is_solid(p, y)) s->T[c] += s->acc[c] / 6.0;
+                if (!t_held(p, x, y)) s->T[c] += s->acc[c] / 6.0;
             }
     }
     /* S8: streaming (Eq. 12) with half-way bounce-back at solid nodes */

@@ -23,6 +23,9 @@ LIB = os.path.join(HERE, "liblbm_oracle.so")
 FREEZE_T = 1
 SINGLE_PHASE = 2
 PERIODIC_Y = 4
+FRAME_T = 8
+FRAME_RHO = 16
+EOS_CS = 32
 
 
 def build(force: bool = False) -> str:
@@ -50,6 +53,7 @@ class OrcParams(C.Structure):
         ("T0", C.c_double), ("Tw", C.c_double),
         ("g_osc", C.c_double), ("period", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("rho_v", C.c_double),
+        ("rho_frame", C.c_double),
         ("flags", C.c_uint32), ("pad_", C.c_int32),
     ]
 
@@ -72,8 +76,11 @@ def lib():
         L.orc_phi.argtypes = [P, C.c_double]
         L.orc_phi.restype = C.c_double
         L.orc_critical.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_critical_cs.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_maxwell.argtypes = [P, C.c_double, dp, dp, dp]
         L.orc_maxwell.restype = C.c_int
+        L.orc_latent_heat.argtypes = [P, C.c_double, dp]
+        L.orc_latent_heat.restype = C.c_int
         L.orc_collide_node.argtypes = [P, dp] + [C.c_double] * 9 + [dp]
         L.orc_heat_rhs.argtypes = [P, dp, dp, dp, dp, dp]
         L.orc_sim_new.argtypes = [P]
@@ -114,6 +121,23 @@ def critical(a: float = 3.0 / 49.0, b: float = 2.0 / 21.0, R: float = 1.0):
     return rc.value, tc.value
 
 
+def critical_cs(a: float = 1.0, b: float = 4.0, R: float = 1.0):
+    """Critical density and temperature of the Carnahan-Starling EOS."""
+    rc, tc = C.c_double(), C.c_double()
+    lib().orc_critical_cs(a, b, R, C.byref(rc), C.byref(tc))
+    return rc.value, tc.value
+
+
+def default_params_cs(Nx: int = 128, Ny: int = 32, **kw) -> OrcParams:
+    """default_params with the Carnahan-Starling EOS (a = 1, b = 4, R = 1),
+    T0 = 0.86 Tc and T_w = 0.80 Tc of its own critical temperature."""
+    _, tc = critical_cs()
+    d = dict(a=1.0, b=4.0, R=1.0, Tc=tc, T0=0.86 * tc, Tw=0.80 * tc, flags=EOS_CS)
+    d.update(kw)
+    d["flags"] = d["flags"] | EOS_CS
+    return default_params(Nx, Ny, **d)
+
+
 def peos(p: OrcParams, rho: float, T: float) -> float:
     return lib().orc_peos(C.byref(p), rho, T)
 
@@ -137,6 +161,19 @@ def maxwell(p: OrcParams, T: float):
     if rc != 0:
         raise ValueError("temperature %g is not below the critical point" % T)
     return g.value, l.value, ps.value
+
+
+def latent_heat(p: OrcParams, T: float) -> float:
+    """Eq. 19 latent heat h_fg at T < Tc."""
+    h = C.c_double()
+    if lib().orc_latent_heat(C.byref(p), T, C.byref(h)) != 0:
+        raise ValueError("temperature %g is not below the critical point" % T)
+    return h.value
+
+
+def jacob(p: OrcParams, T_sat: float, T_w: float) -> float:
+    """Eq. 20: Ja = C_v (T_sat - T_w) / h_fg(T_sat)."""
+    return p.Cv * (T_sat - T_w) / latent_heat(p, T_sat)
 
 
 def matrix_M() -> np.ndarray:

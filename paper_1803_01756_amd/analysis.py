@@ -63,3 +63,21 @@ def field_differences(a, b, periodic_y: bool = False):
     du = np.hypot(a[1] - b[1], a[2] - b[2])[m]
     um = float(np.hypot(b[1], b[2])[m].max())
     return dict(rho=e_rho, u=float(du.max() / um) if um > 0 else float(du.max()), T=e_T)
+
+
+def equivalent_diameter(rho: np.ndarray, rho_l: float, rho_g: float) -> float:
+    """Diameter of the disc holding the same liquid: area = sum of the liquid
+    fraction (rho - rho_g)/(rho_l - rho_g) clipped to [0, 1], D = sqrt(4 A/pi)."""
+    frac = np.clip((rho - rho_g) / (rho_l - rho_g), 0.0, 1.0)
+    return float(np.sqrt(4.0 * frac.sum() / np.pi))
+
+
+def d2_fit(t: np.ndarray, d2: np.ndarray):
+    """Least-squares line d2 = a - K t; returns K and the coefficient of
+    determination R^2."""
+    A = np.column_stack([np.ones_like(t), -t])
+    coef, *_ = np.linalg.lstsq(A, d2, rcond=None)
+    pred = A @ coef
+    ss_res = float(np.sum((d2 - pred) ** 2))
+    ss_tot = float(np.sum((d2 - d2.mean()) ** 2))
+    return float(coef[1]), 1.0 - ss_res / ss_tot if ss_tot > 0 else 1.0

@@ -40,6 +40,7 @@ struct Phys {
     double inv_Cv, lambda;              // Eq. 16
     double g_osc, period;               // drive g_osc sin(2 pi n / period) along +x
     double g_x, g_y, rho_v;             // Eq. 15
+    double rho_frame;                   // reservoir density of a frame
     double rkA, rkB1, rkB2;             // R, a k (1+k)/sqrt(Tc), a k^2 / Tc
     uint32_t flags;                     // LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y
     uint32_t pad_;
@@ -53,6 +54,8 @@ struct Grid {
     int rows;          // stored (fluid) rows
     int y_first;       // y of stored row 0 (1 with plates, 0 periodic)
     int periodic_y;
+    int frame_t;       // T held at T_w on the frame: outermost columns (and rows if periodic_y)
+    int frame_rho;     // the frame is a reservoir at rest with density rho_frame
     int n_strips, n_segs, seg_rows, n_units, n_blocks_pad;
     unsigned plane;    // rows * pitch
 };
@@ -96,7 +99,8 @@ struct Slot {
 
 // Step i of a chunk over every slot of the table (slots sorted by
 // unit_begin, total_units = sum of their units).
-hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, int step_i,
+// ext: some slot uses an optional feature (FRAME_T, FRAME_RHO, EOS_CS)
+hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, int step_i, bool ext,
                                hipStream_t s);
 
 // rho, u (half force) and T at the current time level into device arrays of

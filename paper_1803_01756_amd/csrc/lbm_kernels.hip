@@ -28,7 +28,7 @@
 namespace lbmk {
 namespace {
 
-constexpr uint32_t kFreezeT = 1u, kSinglePhase = 2u;
+constexpr uint32_t kFreezeT = 1u, kSinglePhase = 2u, kEosCS = 32u;
 
 // ---- lane shifts (DPP wave_shr:1 / wave_shl:1) ---------------------------
 // at_xm(v): the value lane l-1 holds (column x-1); at_xp: lane l+1 (x+1).  The
@@ -265,9 +265,20 @@ __device__ __forceinline__ double sqrt_d(double x) {
 //   P = [rho R T D - a s^2 rho^2 (1 - b rho)] / ((1 - b rho) D).
 // kF32: sqrt(T/Tc) in FP32 (its rounding enters phi as a smooth relative
 // error, not a neighbour difference); the FP64 build takes it in FP64.
-template <bool kF32>
+// The Carnahan-Starling option (flag kEosCS), e = b rho / 4:
+//   P = rho R T (1 + e + e^2 - e^3) / (1 - e)^3 - a rho^2.
+// kExt: the build that also serves the optional features (Carnahan-Starling
+// EOS, box frames); the plain build leaves their code out.
+template <bool kF32, bool kExt = true>
 __device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k) {
     constexpr int kNewton = kF32 ? 1 : 2;
+    if (kExt && (k.flags & kEosCS)) {
+        const double e = 0.25 * k.b * rho, o = 1.0 - e;
+        const double Z = (1.0 + e * (1.0 + e * (1.0 - e))) * rcp_d<kNewton>(o * o * o);
+        const double P = rho * (k.R * T * Z - k.a * rho);
+        const double arg = 2.0 * (P - rho * (1.0 / 3.0)) * k.inv_G;
+        return arg > 0.0 ? sqrt_d<kNewton>(arg) : 0.0;
+    }
     const double st = kF32 ? (double)__builtin_amdgcn_sqrtf((float)(T * k.inv_Tc))
                            : sqrt_d<2>(T * k.inv_Tc);
     const double s = 1.0 + k.kappa * (1.0 - st);
@@ -394,14 +405,25 @@ struct Coef {
 };
 template <class R>
 __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, R T_ref,
-                                             const PhysR<R>& pc) {
-    const R br = pc.b * rho;
-    const R omb = (R)1 - br;
-    const R D = (R)1 + br * ((R)2 - br);
-    const R inv = rcp_r(omb * D * rho);  // 1 / ((1 - b rho) D rho)
-    const R A = rho * rho * pc.rkA * D * inv;
-    const R r2D = rho * rho * rho * omb * inv;
-    const R c = pc.inv_Cv * omb * D * inv;
+                                             const PhysR<R>& pc, bool cs) {
+    R A, r2D, c;
+    if (cs) {
+        // Carnahan-Starling: T (dP/dT)_rho = rho R Z(e) T, no sqrt(T) term
+        // (rkB1 = rkB2 = 0); inv = 1 / ((1 - e)^3 rho)
+        const R e = (R)0.25 * pc.b * rho, o = (R)1 - e, o3 = o * o * o;
+        const R inv = rcp_r(o3 * rho);
+        A = rho * rho * pc.rkA * ((R)1 + e * ((R)1 + e * ((R)1 - e))) * inv;
+        r2D = 0;
+        c = pc.inv_Cv * o3 * inv;
+    } else {
+        const R br = pc.b * rho;
+        const R omb = (R)1 - br;
+        const R D = (R)1 + br * ((R)2 - br);
+        const R inv = rcp_r(omb * D * rho);  // 1 / ((1 - b rho) D rho)
+        A = rho * rho * pc.rkA * D * inv;
+        r2D = rho * rho * rho * omb * inv;
+        c = pc.inv_Cv * omb * D * inv;
+    }
     Coef<R> q;
     q.ux = ux;
     q.uy = uy;
@@ -468,8 +490,11 @@ __device__ __forceinline__ int unit_of_block(int nblocks_pad) {
     return ((b & 7) * per + (b >> 3));
 }
 
-// One wave's share of a step: the strip and row segment of `unit`.
-template <class S, bool kMX>
+// One wave's share of a step: the strip and row segment of `unit`.  kExt
+// compiles in the optional features (FRAME_T, FRAME_RHO, EOS_CS); the plain
+// instantiation, used whenever none is set, keeps the register budget of
+// three waves per SIMD.
+template <class S, bool kMX, bool kExt>
 __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bufs<S>& B,
                                           double drive, int unit) {
     using R = typename RealOf<S>::T;
@@ -486,6 +511,18 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     const unsigned xp = (unsigned)(cx == g.Nx - 1 ? 0 : cx + 1);
     const int own_w = min(kOwned, g.Nx - strip * kOwned);
     const bool own_lane = lane >= kHalo && lane < kHalo + own_w;
+    // The frame of a box: the outermost columns, and in a periodic box the
+    // outermost rows.  FRAME_T holds its temperature (the RK right-hand
+    // sides are zeroed there); FRAME_RHO makes it a reservoir at rest
+    // (rho = rho_frame, u = 0, post-collision populations the rest
+    // equilibrium of rho_frame).
+    const bool edge_col = cx == 0 || cx == g.Nx - 1;
+    auto on_frame = [&](const RowK& r) {
+        return edge_col || (g.periodic_y && (r.sr == 0 || r.sr == g.rows - 1));
+    };
+    auto held = [&](const RowK& r) { return kExt && g.frame_t && on_frame(r); };
+    const bool frame_rho = kExt && g.frame_rho != 0;
+    const bool eos_cs = kExt && (k.flags & kEosCS) != 0;
 
     const int ya = g.y_first + seg * g.seg_rows;
     const int yb = min(ya + g.seg_rows, g.y_first + g.rows);
@@ -608,15 +645,19 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                       ((dCur[4] + dCur[5]) + (dCur[6] + dCur[7])) + dCur[8];
                 drd = (double)s;
             }
-            drCur = (R)drd;
-            drdCur = drd;
             jxCur = (dCur[1] - dCur[3]) + (dCur[5] - dCur[6]) + (dCur[8] - dCur[7]);
             jyCur = (dCur[2] - dCur[4]) + (dCur[5] + dCur[6]) - (dCur[7] + dCur[8]);
+            if (frame_rho && on_frame(rA)) {
+                drd = k.rho_frame - k.rho_ref;
+                jxCur = jyCur = 0;
+            }
+            drCur = (R)drd;
+            drdCur = drd;
             const double rho_d = k.rho_ref + drd;
             rhoCur = (R)rho_d;
             dTA = (R)rawT;
             const double Td = k.T_ref + (double)dTA;
-            psiA = tri<double>(psi_eos<sizeof(S) == 4>(rho_d, Td, k));
+            psiA = tri<double>(psi_eos<sizeof(S) == 4, kExt>(rho_d, Td, k));
         } else {
             drCur = 0;
             drdCur = 0.0;
@@ -650,8 +691,10 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             R Fx = (R)Fxd + rho * drive_r + (rho - kr_.rho_v) * kr_.g_x;
             R Fy = (R)Fyd + (rho - kr_.rho_v) * kr_.g_y;
             const R rinv = rcp_r(rho);
-            const R ux = (jxPrv + (R)0.5 * Fx) * rinv;
-            const R uy = (jyPrv + (R)0.5 * Fy) * rinv;
+            R ux = (jxPrv + (R)0.5 * Fx) * rinv;
+            R uy = (jyPrv + (R)0.5 * Fy) * rinv;
+            const bool resB = frame_rho && on_frame(rB);
+            if (resB) ux = uy = 0;
             uxB = tri<R>(ux);
             uyB = tri<R>(uy);
             if (kr - 1 >= ya && kr - 1 < yb) {
@@ -667,6 +710,12 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
 #pragma unroll
                 for (int q = 0; q < 9; ++q) dn[q] = dPrv[q];
                 collide<R>(dn, drPrv, rho, rinv, ux, uy, Fx, Fy, th, sv, cv);
+                if (resB) {
+                    const double dr = k.rho_frame - k.rho_ref;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q)
+                        dn[q] = (R)((q == 0 ? 4.0 / 9 : (q < 5 ? 1.0 / 9 : 1.0 / 36)) * dr);
+                }
                 if (own_lane) {
                     const unsigned so = B.fout + (unsigned)rB.sr * rowb;
                     if (kMX) {
@@ -699,8 +748,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             Tri<R> t1;
             if (rC.fluid && needC) {
                 const R dv = div_u<R>(ux3, ux2, ux1, uy3, uy2, uy1);
-                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, cv);
-                const R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
+                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, cv, eos_cs);
+                R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
+                if (held(rC)) h1 = 0;
                 acc2 = h1;
                 t1 = tri<R>(tn2.c + (R)0.5 * h1);
             } else {
@@ -712,7 +762,8 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             const RowK rD = row_info(kr - 3, g);
             Tri<R> t2;
             if (rD.fluid && needD) {
-                const R h2 = heat_rhs<R>(t1c, t1b, t1a, cf3, T_ref);
+                R h2 = heat_rhs<R>(t1c, t1b, t1a, cf3, T_ref);
+                if (held(rD)) h2 = 0;
                 acc3 += (R)2 * h2;
                 t2 = tri<R>(tn3.c + (R)0.5 * h2);
             } else {
@@ -723,7 +774,8 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             const RowK rE = row_info(kr - 4, g);
             Tri<R> t3;
             if (rE.fluid && needE) {
-                const R h3 = heat_rhs<R>(t2c, t2b, t2a, cf4, T_ref);
+                R h3 = heat_rhs<R>(t2c, t2b, t2a, cf4, T_ref);
+                if (held(rE)) h3 = 0;
                 acc4 += (R)2 * h3;
                 t3 = tri<R>(tn4 + h3);
             } else {
@@ -741,7 +793,8 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         if (!freezeT) {
             const RowK rF = row_info(kr - 5, g);
             if (rF.fluid && kr - 5 >= ya && kr - 5 < yb) {
-                const R h4 = heat_rhs<R>(t3c, t3b, t3a, cf5, T_ref);
+                R h4 = heat_rhs<R>(t3c, t3b, t3a, cf5, T_ref);
+                if (held(rF)) h4 = 0;
                 const R tnew = tn5 + (acc5 + h4) * ((R)1 / 6);
                 if (own_lane) bstore((S)tnew, rb, vx, B.Tout + (unsigned)rF.sr * rowb);
             }
@@ -798,24 +851,26 @@ __device__ __forceinline__ int wave_in_block() {
 
 // The FP64 build has its own kernel: it needs about 256 registers and runs
 // one wave per SIMD, the FP32 builds fit three.
-template <class S, bool kMX>
+template <class S, bool kMX, bool kExt>
 __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Phys k, Bufs<S> B,
                                                                         long long n) {
     const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
     if (unit >= g.n_units) return;  // whole waves only
-    step_unit<S, kMX>(g, k, B, drive_at(k, n), unit);
+    step_unit<S, kMX, kExt>(g, k, B, drive_at(k, n), unit);
 }
 
+template <bool kExt>
 __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel_f64(Grid g, Phys k,
                                                                         Bufs<double> B,
                                                                         long long n) {
     const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
     if (unit >= g.n_units) return;
-    step_unit<double, false>(g, k, B, drive_at(k, n), unit);
+    step_unit<double, false, kExt>(g, k, B, drive_at(k, n), unit);
 }
 
 // Step i of a chunk over a batch of channels.  The slot of a unit is found by
 // a binary search over the slots' first units (wave-uniform).
+template <bool kExt>
 __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_batched_kernel(
     const Slot* __restrict__ slots, int n_slots, int total_units, int nblocks_pad, int step_i) {
     const int unit = unit_of_block(nblocks_pad) * kWavesPerBlock + wave_in_block();
@@ -845,10 +900,16 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_batched_kernel(
         B.Tin = sl.off_T[t];
         B.Tout = sl.off_T[t ^ 1];
     }
-    step_unit<float, false>(g, k, B, drive_at(k, sl.n0 + step_i), unit - sl.unit_begin);
+    step_unit<float, false, kExt>(g, k, B, drive_at(k, sl.n0 + step_i), unit - sl.unit_begin);
 }
 
 // ---- moments: two passes over all nodes ------------------------------------
+// a node of a FRAME_RHO reservoir (y counts the plate rows)
+__device__ __forceinline__ bool reservoir_node(const Grid& g, int cx, int y) {
+    return g.frame_rho &&
+           (cx == 0 || cx == g.Nx - 1 || (g.periodic_y && (y == 0 || y == g.Ny - 1)));
+}
+
 // pass 1: rho, psi, j (and T) per node into scratch; pass 2: forces and u.
 template <class S, bool kMX>
 __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __restrict__ f,
@@ -881,6 +942,8 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
 #pragma unroll
     for (int q = 0; q < 9; ++q) dr += (double)d[q];
     if (kMX) dr += (double)f0lo[(unsigned)r.sr * (unsigned)g.pitch + x];
+    const bool res = reservoir_node(g, cx, y);
+    if (res) dr = k.rho_frame - k.rho_ref;
     const double rho = k.rho_ref + dr;
     const double Td = k.T_ref + (double)T[(unsigned)r.sr * (unsigned)g.pitch + x];
     rho_out[i] = rho;
@@ -890,6 +953,7 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
             ((double)d[8] - (double)d[7]);
     jy[i] = ((double)d[2] - (double)d[4]) + ((double)d[5] + (double)d[6]) -
             ((double)d[7] + (double)d[8]);
+    if (res) jx[i] = jy[i] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
@@ -935,6 +999,7 @@ __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
     Fy += (rho - k.rho_v) * k.g_y;
     ux_out[i] = (jx[i] + 0.5 * Fx) / rho;
     uy_out[i] = (jy[i] + 0.5 * Fy) / rho;
+    if (reservoir_node(g, cx, y)) ux_out[i] = uy_out[i] = 0.0;
 }
 
 // ---- initial state ----------------------------------------------------------
@@ -975,7 +1040,10 @@ __global__ __launch_bounds__(256) void init_kernel(Grid g, Phys k, const double*
             f[q * g.plane + o] = (S)v;
         }
     }
-    T[o] = (S)0;  // T = T_0 = T_ref
+    // T = T_0 = T_ref, or T_w on a held frame node
+    const bool held = g.frame_t && (cx == 0 || cx == g.Nx - 1 ||
+                                    (g.periodic_y && (y == 0 || y == g.Ny - 1)));
+    T[o] = held ? (S)k.dT_wall : (S)0;
 }
 
 // ---- deterministic FP64 reduction ------------------------------------------
@@ -1051,12 +1119,20 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
     return hipGetLastError();
 }
 
+bool needs_ext(const Grid& g, const Phys& k) {
+    return g.frame_t || g.frame_rho || (k.flags & kEosCS);
+}
+
 template <class S, bool kMX>
 static hipError_t step_impl(const Grid& g, const Phys& k, const Bufs<S>& b, int64_t n,
                             hipStream_t s) {
     if (g.n_units <= 0) return hipSuccess;
-    hipLaunchKernelGGL((step_kernel<S, kMX>), dim3(g.n_blocks_pad), dim3(kLanes * kWavesPerBlock),
-                       0, s, g, k, b, (long long)n);
+    if (needs_ext(g, k))
+        hipLaunchKernelGGL((step_kernel<S, kMX, true>), dim3(g.n_blocks_pad),
+                           dim3(kLanes * kWavesPerBlock), 0, s, g, k, b, (long long)n);
+    else
+        hipLaunchKernelGGL((step_kernel<S, kMX, false>), dim3(g.n_blocks_pad),
+                           dim3(kLanes * kWavesPerBlock), 0, s, g, k, b, (long long)n);
     return hipGetLastError();
 }
 
@@ -1068,18 +1144,26 @@ hipError_t launch_step_f32(const Grid& g, const Phys& k, const Bufs<float>& b, b
 hipError_t launch_step_f64(const Grid& g, const Phys& k, const Bufs<double>& b, int64_t n,
                            hipStream_t s) {
     if (g.n_units <= 0) return hipSuccess;
-    hipLaunchKernelGGL(step_kernel_f64, dim3(g.n_blocks_pad), dim3(kLanes * kWavesPerBlock), 0, s,
-                       g, k, b, (long long)n);
+    if (needs_ext(g, k))
+        hipLaunchKernelGGL(step_kernel_f64<true>, dim3(g.n_blocks_pad),
+                           dim3(kLanes * kWavesPerBlock), 0, s, g, k, b, (long long)n);
+    else
+        hipLaunchKernelGGL(step_kernel_f64<false>, dim3(g.n_blocks_pad),
+                           dim3(kLanes * kWavesPerBlock), 0, s, g, k, b, (long long)n);
     return hipGetLastError();
 }
 
 hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, int step_i,
-                               hipStream_t s) {
+                               bool ext, hipStream_t s) {
     if (total_units <= 0 || n_slots <= 0) return hipSuccess;
     const int nb = (total_units + kWavesPerBlock - 1) / kWavesPerBlock;
     const int nbp = (nb + 7) / 8 * 8;
-    hipLaunchKernelGGL(step_batched_kernel, dim3(nbp), dim3(kLanes * kWavesPerBlock), 0, s, slots,
-                       n_slots, total_units, nbp, step_i);
+    if (ext)
+        hipLaunchKernelGGL(step_batched_kernel<true>, dim3(nbp), dim3(kLanes * kWavesPerBlock), 0,
+                           s, slots, n_slots, total_units, nbp, step_i);
+    else
+        hipLaunchKernelGGL(step_batched_kernel<false>, dim3(nbp), dim3(kLanes * kWavesPerBlock), 0,
+                           s, slots, n_slots, total_units, nbp, step_i);
     return hipGetLastError();
 }
 

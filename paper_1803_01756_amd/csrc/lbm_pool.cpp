@@ -181,8 +181,8 @@ lbm_status lbm_pool_admit(lbm_pool* P, const lbm_params* pin, const double* rho0
         for (int y = per ? 0 : 1; y < (per ? p.Ny : p.Ny - 1); ++y)
             for (int x = 0; x < p.Nx; ++x) {
                 const double r = rho0[(size_t)y * p.Nx + x];
-                if (!(r > 0.0 && p.b * r < 1.0))
-                    return fail(LBM_EINVAL, "initial density %g outside (0, 1/b)", r);
+                if (!(r > 0.0 && p.b * r < ((p.flags & LBM_EOS_CS) ? 4.0 : 1.0)))
+                    return fail(LBM_EINVAL, "initial density %g outside the EOS range", r);
             }
     PCHK(hipSetDevice(P->dev));
     st = ensure_mom(P, cells);
@@ -279,8 +279,10 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
     PCHK(hipEventSynchronize(P->table_free[b]));  // the staging copy from two chunks ago
     lbmk::Slot* tab = P->table_host[b];
     int units = 0, longest = 0;
+    bool ext = false;  // some slot needs the build with the optional features
     for (size_t j = 0; j < act.size(); ++j) {
         SlotState& s = P->slots[act[j]];
+        ext = ext || (s.p.flags & (LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS));
         if (!s.ready_waited) {
             PCHK(hipStreamWaitEvent(P->main, s.ready, 0));
             s.ready_waited = true;
@@ -307,7 +309,7 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
                         P->main));
     PCHK(hipEventRecord(P->table_free[b], P->main));
     for (int i = 0; i < longest; ++i)
-        PCHK(lbmk::launch_step_batched(P->table_dev, (int)act.size(), units, i, P->main));
+        PCHK(lbmk::launch_step_batched(P->table_dev, (int)act.size(), units, i, ext, P->main));
     for (size_t j = 0; j < act.size(); ++j) {
         SlotState& s = P->slots[act[j]];
         const int take = (int)std::min<int64_t>(chunk, s.steps_left);

@@ -49,25 +49,44 @@ namespace {
 // ---- Peng-Robinson thermodynamics (Eq. 11), host FP64 -------------------
 double kappa_of(double omega) { return 0.37464 + 1.54226 * omega - 0.26992 * omega * omega; }
 
+// With cs set, the Carnahan-Starling EOS (eta = b rho / 4):
+//   P = rho R T (1 + eta + eta^2 - eta^3) / (1 - eta)^3 - a rho^2.
 struct Eos {
     double a, b, R, k, Tc;
+    bool cs = false;
     double phi(double T) const {
         const double s = 1.0 + k * (1.0 - std::sqrt(T / Tc));
         return s * s;
     }
+    double rmax() const { return cs ? 4.0 / b : 1.0 / b; }  // packing limit
     double P(double r, double T) const {
         const double br = b * r;
+        if (cs) {
+            const double e = 0.25 * br, o = 1.0 - e;
+            return r * R * T * (1.0 + e * (1.0 + e * (1.0 - e))) / (o * o * o) - a * r * r;
+        }
         return r * R * T / (1.0 - br) - a * phi(T) * r * r / (1.0 + 2.0 * br - br * br);
     }
     double dPdr(double r, double T) const {
         const double br = b * r, D = 1.0 + 2.0 * br - br * br;
+        if (cs) {
+            const double e = 0.25 * br, o = 1.0 - e, o2 = o * o;
+            return R * T * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (o2 * o2) -
+                   2.0 * a * r;
+        }
         return R * T / ((1.0 - br) * (1.0 - br)) - 2.0 * a * phi(T) * r * (1.0 + br) / (D * D);
     }
     // chemical potential from the Helmholtz free energy of Eq. 11:
     // f = rho R T [ln(rho/(1 - b rho)) - 1]
     //     - a phi rho / (2 sqrt2 b) ln[(1 + (1+sqrt2) b rho) / (1 + (1-sqrt2) b rho)],
     // mu = df/drho (the additive constant drops out of equalities)
+    // CS: f = rho R T [ln rho - 1 + (4 eta - 3 eta^2)/(1 - eta)^2] - a rho^2
     double mu(double r, double T) const {
+        if (cs) {
+            const double e = 0.25 * b * r, o = 1.0 - e;
+            return R * T * (std::log(r) + e * (8.0 + e * (-9.0 + 3.0 * e)) / (o * o * o)) -
+                   2.0 * a * r;
+        }
         const double br = b * r, s2 = std::sqrt(2.0);
         const double L = std::log((1.0 + (1.0 + s2) * br) / (1.0 + (1.0 - s2) * br));
         return R * T * (std::log(r / (1.0 - br)) + br / (1.0 - br)) -
@@ -93,6 +112,37 @@ void critical_point(double a, double b, double R, double* rho_c, double* T_c) {
     *T_c = 2.0 * a / (b * R) * e * (1.0 + e) * (1.0 - e) * (1.0 - e) / (D * D);
 }
 
+// CS critical point: on the spinodal T(eta) is proportional to
+// eta (1 - eta)^4 / (1 + 4 eta + 4 eta^2 - 4 eta^3 + eta^4); bisection on the
+// zero of its logarithmic derivative.
+void critical_point_cs(double a, double b, double R, double* rho_c, double* T_c) {
+    auto q = [](double e) { return 1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e))); };
+    auto dlog = [&](double e) {
+        const double dq = 4.0 + e * (8.0 + e * (-12.0 + 4.0 * e));
+        return 1.0 / e - 4.0 / (1.0 - e) - dq / q(e);
+    };
+    double lo = 1e-6, hi = 1.0 - 1e-6;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (dlog(mid) > 0.0) lo = mid; else hi = mid;
+    }
+    const double e = 0.5 * (lo + hi), o = 1.0 - e;
+    *rho_c = 4.0 * e / b;
+    *T_c = 2.0 * a * (*rho_c) * o * o * o * o / (R * q(e));
+}
+
+// the critical point of the EOS that the flags select
+void critical_of(const lbm_params& p, double* rho_c, double* T_c) {
+    if (p.flags & LBM_EOS_CS) critical_point_cs(p.a, p.b, p.R, rho_c, T_c);
+    else critical_point(p.a, p.b, p.R, rho_c, T_c);
+}
+
+Eos eos_of(const lbm_params& p, double Tc) {
+    Eos E{p.a, p.b, p.R, kappa_of(p.omega), Tc};
+    E.cs = (p.flags & LBM_EOS_CS) != 0;
+    return E;
+}
+
 template <class F>
 double bisect(F f, double lo, double hi) {
     const double flo = f(lo);
@@ -107,7 +157,7 @@ double bisect(F f, double lo, double hi) {
 // pressure p between the spinodal pressures the vapour and liquid roots of
 // P = p are bracketed; mu(liquid) - mu(vapour) changes sign at p_sat.
 bool coexistence(const Eos& E, double T, double* rg, double* rl, double* ps) {
-    const double rmax = 1.0 / E.b;
+    const double rmax = E.rmax();
     const int n = 4000;
     double s1 = -1.0, s2 = -1.0;
     double prev = E.dPdr(rmax * 1e-6, T);
@@ -181,7 +231,9 @@ lbm_status validate(const lbm_params& p) {
     if (p.Ny < (per ? 3 : 4)) return fail(LBM_EINVAL, "Ny = %d too small", p.Ny);
     if (p.precision < LBM_FP32_DEV || p.precision > LBM_FP32_DEV_MASSEXACT)
         return fail(LBM_EINVAL, "unknown precision %d", p.precision);
-    if (p.flags & ~7u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & ~63u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if ((p.flags & LBM_FRAME_RHO) && !(p.rho_frame > 0.0))
+        return fail(LBM_EINVAL, "LBM_FRAME_RHO needs rho_frame > 0");
     if (p.G == 0.0) return fail(LBM_EINVAL, "G must be nonzero");
     const double rates[5] = {p.s_rho, p.s_e, p.s_zeta, p.s_j, p.s_q};
     for (double s : rates)
@@ -256,6 +308,8 @@ void fill_grid(const lbm_params& p, const Layout& L, int seg_rows, Grid& g) {
     g.pitch = L.pitch;
     g.rows = L.rows;
     g.periodic_y = (p.flags & LBM_PERIODIC_Y) ? 1 : 0;
+    g.frame_t = (p.flags & LBM_FRAME_T) ? 1 : 0;
+    g.frame_rho = (p.flags & LBM_FRAME_RHO) ? 1 : 0;
     g.y_first = g.periodic_y ? 0 : 1;
     g.plane = (unsigned)L.plane;
     g.n_strips = (p.Nx + lbmk::kOwned - 1) / lbmk::kOwned;
@@ -299,9 +353,14 @@ void fill_phys(const lbm_params& p, Phys& k) {
     k.g_x = p.g_x;
     k.g_y = p.g_y;
     k.rho_v = p.rho_v;
+    k.rho_frame = p.rho_frame;
     k.rkA = p.R;
     k.rkB1 = p.a * kap * (1.0 + kap) / std::sqrt(p.T_c);
     k.rkB2 = p.a * kap * kap / p.T_c;
+    if (p.flags & LBM_EOS_CS) {  // no temperature-dependent attraction
+        k.kappa = 0.0;
+        k.rkB1 = k.rkB2 = 0.0;
+    }
     k.flags = p.flags;
     auto fillr = [&](auto& r) {
         using T = std::remove_reference_t<decltype(r.b)>;
@@ -432,13 +491,20 @@ lbm_status lbm_eos_critical(double a, double b, double R, double* rho_c, double*
     return LBM_OK;
 }
 
+lbm_status lbm_eos_critical_cs(double a, double b, double R, double* rho_c, double* T_c) {
+    if (!(a > 0 && b > 0 && R > 0) || !rho_c || !T_c)
+        return fail(LBM_EINVAL, "EOS constants must be positive");
+    critical_point_cs(a, b, R, rho_c, T_c);
+    return LBM_OK;
+}
+
 lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_g, double* rho_l,
                                double* p_sat) {
     if (!p || !rho_g || !rho_l || !p_sat) return fail(LBM_EINVAL, "null argument");
     double Tc = p->T_c, rc;
-    if (!(Tc > 0.0)) critical_point(p->a, p->b, p->R, &rc, &Tc);
+    if (!(Tc > 0.0)) critical_of(*p, &rc, &Tc);
     if (!(T > 0.0 && T < Tc)) return fail(LBM_EINVAL, "T = %g is not below Tc = %g", T, Tc);
-    Eos E{p->a, p->b, p->R, kappa_of(p->omega), Tc};
+    const Eos E = eos_of(*p, Tc);
     if (!coexistence(E, T, rho_g, rho_l, p_sat))
         return fail(LBM_EINVAL, "no coexistence found at T = %g", T);
     return LBM_OK;
@@ -446,15 +512,37 @@ lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_g, dou
 
 lbm_status lbm_eos_pressure(const lbm_params* p, double rho, double T, double* P, double* psi) {
     if (!p) return fail(LBM_EINVAL, "null params");
-    if (!(rho > 0.0 && p->b * rho < 1.0 && T > 0.0)) return fail(LBM_EINVAL, "rho or T out of range");
     if (p->G == 0.0) return fail(LBM_EINVAL, "G must be nonzero");
     double Tc = p->T_c, rc;
-    if (!(Tc > 0.0)) critical_point(p->a, p->b, p->R, &rc, &Tc);
-    Eos E{p->a, p->b, p->R, kappa_of(p->omega), Tc};
+    if (!(Tc > 0.0)) critical_of(*p, &rc, &Tc);
+    const Eos E = eos_of(*p, Tc);
+    if (!(rho > 0.0 && rho < E.rmax() && T > 0.0)) return fail(LBM_EINVAL, "rho or T out of range");
     const double pe = E.P(rho, T);
     const double arg = 2.0 * (pe - rho / 3.0) / p->G;
     if (P) *P = pe;
     if (psi) *psi = arg > 0.0 ? std::sqrt(arg) : 0.0;
+    return LBM_OK;
+}
+
+lbm_status lbm_eos_latent_heat(const lbm_params* p, double T, double* h_fg) {
+    if (!p || !h_fg) return fail(LBM_EINVAL, "null argument");
+    double rg, rl, ps;
+    const lbm_status st = lbm_eos_coexistence(p, T, &rg, &rl, &ps);
+    if (st != LBM_OK) return st;
+    if (p->flags & LBM_EOS_CS) {  // T-independent attraction a rho^2: du = -a drho
+        *h_fg = p->a * (rl - rg) + ps * (1.0 / rg - 1.0 / rl);
+        return LBM_OK;
+    }
+    double Tc = p->T_c, rc;
+    if (!(Tc > 0.0)) critical_point(p->a, p->b, p->R, &rc, &Tc);
+    const double k = kappa_of(p->omega), b = p->b, s2 = std::sqrt(2.0);
+    const double sq = std::sqrt(T / Tc), s = 1.0 + k * (1.0 - sq);
+    // a phi - T a phi' with phi = s^2, T phi' = -k s sqrt(T/Tc)
+    const double attr = p->a * (s * s + k * s * sq);
+    auto L = [&](double r) {
+        return std::log((1.0 + (1.0 + s2) * b * r) / (1.0 + (1.0 - s2) * b * r));
+    };
+    *h_fg = attr / (2.0 * s2 * b) * (L(rl) - L(rg)) + ps * (1.0 / rg - 1.0 / rl);
     return LBM_OK;
 }
 
@@ -463,7 +551,7 @@ lbm_status lbm_params_resolve(lbm_params* p) {
     if (!(p->a > 0 && p->b > 0 && p->R > 0)) return fail(LBM_EINVAL, "EOS constants must be positive");
     if (!(p->T_c > 0.0)) {
         double rc;
-        critical_point(p->a, p->b, p->R, &rc, &p->T_c);
+        critical_of(*p, &rc, &p->T_c);
     }
     if (!(p->T_0 > 0.0)) p->T_0 = 0.86 * p->T_c;
     if (!(p->T_w > 0.0)) p->T_w = 0.80 * p->T_c;
@@ -506,8 +594,8 @@ lbm_status lbm_create(const lbm_params* pin, const double* rho0, void* workspace
     for (int y = per ? 0 : 1; y < (per ? p.Ny : p.Ny - 1); ++y)
         for (int x = 0; x < p.Nx; ++x) {
             const double r = r0[(size_t)y * p.Nx + x];
-            if (!(r > 0.0 && p.b * r < 1.0))
-                return fail(LBM_EINVAL, "initial density %g at (%d, %d) outside (0, 1/b)", r, x, y);
+            if (!(r > 0.0 && p.b * r < ((p.flags & LBM_EOS_CS) ? 4.0 : 1.0)))
+                return fail(LBM_EINVAL, "initial density %g at (%d, %d) outside the EOS range", r, x, y);
         }
 
     lbm_sim* s = new (std::nothrow) lbm_sim();
@@ -638,7 +726,7 @@ lbm_status lbm_save(lbm_sim* s, void* host, size_t bytes) {
     HIPCHK(hipSetDevice(s->dev));
     CkptHeader h;
     std::memset(&h, 0, sizeof(h));
-    std::memcpy(h.magic, "LBMCKPT1", 8);
+    std::memcpy(h.magic, "LBMCKPT2", 8);
     h.n = s->n;
     h.p = s->p;
     char* dst = static_cast<char*>(host);
@@ -661,7 +749,7 @@ lbm_status lbm_load(lbm_sim* s, const void* host, size_t bytes) {
     if (bytes < lbm_state_bytes(s)) return fail(LBM_EINVAL, "buffer too small");
     CkptHeader h;
     std::memcpy(&h, host, sizeof(h));
-    if (std::memcmp(h.magic, "LBMCKPT1", 8) != 0) return fail(LBM_EINVAL, "not a checkpoint");
+    if (std::memcmp(h.magic, "LBMCKPT2", 8) != 0) return fail(LBM_EINVAL, "not a checkpoint");
     if (h.p.Nx != s->p.Nx || h.p.Ny != s->p.Ny || h.p.precision != s->p.precision ||
         (h.p.flags & LBM_PERIODIC_Y) != (s->p.flags & LBM_PERIODIC_Y))
         return fail(LBM_EINVAL, "checkpoint grid or precision differs");

@@ -74,3 +74,13 @@ def poisson_arrivals(n: int, rate: float, seed: int = 20):
     gaps = rng.exponential(1.0 / rate, size=n)
     steps = rng.integers(2000, 20001, size=n)
     return np.cumsum(gaps), steps
+
+
+def droplet_disc(Nx: int, Ny: int, D: float, rho_in: float, rho_out: float,
+                 width: float = 5.0) -> np.ndarray:
+    """Density field [Ny, Nx] of a disc of diameter D at the centre
+    ((Nx-1)/2, (Ny-1)/2): a tanh profile of the given width from rho_in
+    inside to rho_out outside."""
+    y, x = np.mgrid[0:Ny, 0:Nx].astype(float)
+    r = np.hypot(x - (Nx - 1) / 2, y - (Ny - 1) / 2)
+    return 0.5 * (rho_in + rho_out) - 0.5 * (rho_in - rho_out) * np.tanh(2 * (r - D / 2) / width)

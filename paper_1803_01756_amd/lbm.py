@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "liblbm_hip.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_FP32_DEV, LBM_FP64, LBM_FP32_DEV_MASSEXACT = 0, 1, 2
-LBM_FREEZE_T, LBM_SINGLE_PHASE, LBM_PERIODIC_Y = 1, 2, 4
+LBM_FREEZE_T, LBM_SINGLE_PHASE, LBM_PERIODIC_Y, LBM_FRAME_T, LBM_FRAME_RHO, LBM_EOS_CS = 1, 2, 4, 8, 16, 32
 
 _STATUS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EDEVICE: "EDEVICE",
            LBM_EUNSTABLE: "EUNSTABLE", LBM_ESTATE: "ESTATE"}
@@ -45,7 +45,7 @@ class lbm_params(C.Structure):
         ("T_0", C.c_double), ("T_w", C.c_double),
         ("g_osc", C.c_double), ("period", C.c_double),
         ("g_x", C.c_double), ("g_y", C.c_double), ("rho_v", C.c_double),
-        ("rho_ref", C.c_double),
+        ("rho_ref", C.c_double), ("rho_frame", C.c_double),
         ("precision", C.c_int32), ("flags", C.c_uint32),
     ]
 
@@ -80,8 +80,10 @@ def lib():
             "lbm_params_default": (None, [P]),
             "lbm_params_resolve": (C.c_int, [P]),
             "lbm_eos_critical": (C.c_int, [C.c_double, C.c_double, C.c_double, dp, dp]),
+            "lbm_eos_critical_cs": (C.c_int, [C.c_double, C.c_double, C.c_double, dp, dp]),
             "lbm_eos_coexistence": (C.c_int, [P, C.c_double, dp, dp, dp]),
             "lbm_eos_pressure": (C.c_int, [P, C.c_double, C.c_double, dp, dp]),
+            "lbm_eos_latent_heat": (C.c_int, [P, C.c_double, dp]),
             "lbm_workspace_bytes": (C.c_size_t, [P]),
             "lbm_create": (C.c_int, [P, dp, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "lbm_step": (C.c_int, [vp, C.c_int64]),
@@ -125,8 +127,9 @@ def lib():
 
 def exported_symbols():
     """Names the header declares; the CPU tests check the library has them."""
-    return ["lbm_params_default", "lbm_params_resolve", "lbm_eos_critical",
-            "lbm_eos_coexistence", "lbm_eos_pressure", "lbm_workspace_bytes", "lbm_create", "lbm_step",
+    return ["lbm_params_default", "lbm_params_resolve", "lbm_eos_critical", "lbm_eos_critical_cs",
+            "lbm_eos_coexistence", "lbm_eos_pressure", "lbm_eos_latent_heat",
+            "lbm_workspace_bytes", "lbm_create", "lbm_step",
             "lbm_moments", "lbm_reduce", "lbm_synchronize", "lbm_destroy", "lbm_time",
             "lbm_get_params", "lbm_last_error", "lbm_state_bytes", "lbm_save", "lbm_load",
             "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_bandwidth_probe",
@@ -169,10 +172,28 @@ def lbm_eos_critical(a=3.0 / 49.0, b=2.0 / 21.0, R=1.0):
     return rc.value, tc.value
 
 
+def lbm_eos_critical_cs(a=1.0, b=4.0, R=1.0):
+    rc, tc = C.c_double(), C.c_double()
+    _check(lib().lbm_eos_critical_cs(a, b, R, C.byref(rc), C.byref(tc)))
+    return rc.value, tc.value
+
+
 def lbm_eos_coexistence(p: lbm_params, T: float):
     g, l, ps = C.c_double(), C.c_double(), C.c_double()
     _check(lib().lbm_eos_coexistence(C.byref(p), T, C.byref(g), C.byref(l), C.byref(ps)))
     return g.value, l.value, ps.value
+
+
+def lbm_eos_latent_heat(p: lbm_params, T: float) -> float:
+    """h_fg of Eq. 19 at T < T_c."""
+    h = C.c_double()
+    _check(lib().lbm_eos_latent_heat(C.byref(p), T, C.byref(h)))
+    return h.value
+
+
+def jacob_number(p: lbm_params, T_sat: float, T_w: float) -> float:
+    """Eq. 20: Ja = C_v (T_sat - T_w) / h_fg(T_sat)."""
+    return p.C_v * (T_sat - T_w) / lbm_eos_latent_heat(p, T_sat)
 
 
 def lbm_eos_pressure(p: lbm_params, rho: float, T: float):

@@ -12,7 +12,8 @@ _MAP = dict(Nx="Nx", Ny="Ny", a="a", b="b", R="R", omega="omega", T_c="Tc", G="G
             theta="theta", G_w="Gw", psi_w="psiw", s_rho="s_rho", s_e="s_e",
             s_zeta="s_zeta", s_j="s_j", s_q="s_q", tau_g="tau_g", tau_l="tau_l",
             rho_g="rho_g", rho_l="rho_l", C_v="Cv", lambda_="lam", T_0="T0", T_w="Tw",
-            g_osc="g_osc", period="period", g_x="gx", g_y="gy", rho_v="rho_v", flags="flags")
+            g_osc="g_osc", period="period", g_x="gx", g_y="gy", rho_v="rho_v",
+            rho_frame="rho_frame", flags="flags")
 
 
 def to_oracle(orc, p):

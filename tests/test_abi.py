@@ -7,7 +7,7 @@ import re
 import numpy as np
 import pytest
 
-from paper_1803_01756_amd import lbm
+from paper_1803_01756_amd import configs, lbm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -62,7 +62,7 @@ def test_library_coexistence_matches_oracle(L, orc, frac):
 
 @pytest.mark.parametrize("bad", [dict(Nx=2), dict(Ny=3), dict(s_e=0.9), dict(s_q=2.0),
                                  dict(tau_g=0.5), dict(G=0.0), dict(precision=7),
-                                 dict(flags=64)])
+                                 dict(flags=64), dict(flags=128)])
 def test_workspace_bytes_rejects_invalid(L, bad):
     p = lbm.lbm_params_default(**bad)
     assert lbm.lbm_workspace_bytes(p) == 0
@@ -104,3 +104,42 @@ def test_contact_angle_table_matches_golden():
     angles = [a for _, a in sorted(configs.CONTACT_ANGLE_TABLE)]
     assert all(x > y for x, y in zip(angles, angles[1:]))
     assert abs(configs.wall_fraction_for_angle(90.13) - 0.45) < 1e-9
+
+
+@pytest.mark.parametrize("frac", [0.56, 0.65, 0.86, 0.95])
+def test_latent_heat_matches_oracle(orc, frac):
+    """The library's Eq. 19 (written with the log of the free-energy term)
+    against the oracle's (the printed log ratio), and Eq. 20."""
+    p = lbm.lbm_params_resolve(lbm.lbm_params_default())
+    q = orc.default_params()
+    T = frac * p.T_c
+    h = lbm.lbm_eos_latent_heat(p, T)
+    assert h == pytest.approx(orc.latent_heat(q, T), rel=1e-9)
+    assert lbm.jacob_number(p, T, 0.5 * p.T_c) == pytest.approx(
+        orc.jacob(q, T, 0.5 * p.T_c), rel=1e-9)
+
+
+def test_latent_heat_rejects_supercritical():
+    p = lbm.lbm_params_resolve(lbm.lbm_params_default())
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_eos_latent_heat(p, 1.01 * p.T_c)
+
+
+def test_cs_eos_matches_oracle(orc):
+    """Carnahan-Starling option: critical point, coexistence and latent heat
+    from the library's host EOS against the oracle's."""
+    rc, tc = lbm.lbm_eos_critical_cs()
+    orc_rc, orc_tc = orc.critical_cs()
+    assert tc == pytest.approx(orc_tc, rel=1e-12)
+    assert rc == pytest.approx(orc_rc, rel=1e-6)  # flat maximum: T_c is sharp, rho_c is not
+    p = configs.channel_params_cs(32, 8)
+    q = orc.default_params_cs()
+    for frac in (0.6, 0.86, 0.95):
+        T = frac * tc
+        g, l, ps = lbm.lbm_eos_coexistence(p, T)
+        og, ol, ops = orc.maxwell(q, T)
+        assert g == pytest.approx(og, rel=1e-9) and l == pytest.approx(ol, rel=1e-10)
+        assert lbm.lbm_eos_latent_heat(p, T) == pytest.approx(orc.latent_heat(q, T), rel=1e-9)
+    for rho in (0.02, 0.13, 0.3):
+        P, psi = lbm.lbm_eos_pressure(p, rho, 0.8 * tc)
+        assert P == pytest.approx(orc.peos(q, rho, 0.8 * tc), rel=1e-13)

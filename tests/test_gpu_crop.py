@@ -5,10 +5,14 @@ tests/golden/crop_<Nx>x<Ny>_droplets.json (written by
 oracle/crop_droplet_stats.py from the same parameters and seed).
 
 Every 10000 steps up to 50000: droplets on each plate (count, mean spacing),
-condensed volume, and the x-averaged profiles of rho, T and u_x.  While the
-vapour is metastable the fields stay smooth and the profiles must agree to
-the accumulated FP32 rounding; once droplets nucleate their positions depend
-on rounding, so the statistics are compared with a tolerance.
+condensed volume, and the x-averaged profiles of rho, T and u_x, for the FP64
+build (droplet for droplet) and mass-exact FP32 storage (profiles while the
+vapour is metastable; statistics once droplets nucleate, since their
+arrangement then depends on rounding).
+
+Two crops: 512 x 64 (a low channel whose vapour stays metastable: no
+droplets) and 256 x 512 (the full height: a film forms, breaks into droplets
+by step 20000, and they coarsen).
 """
 import glob
 import json
@@ -25,14 +29,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = sorted(glob.glob(os.path.join(HERE, "golden", "crop_*_droplets.json")))
 
 
+@pytest.mark.parametrize("precision", [lbm.LBM_FP32_DEV_MASSEXACT, lbm.LBM_FP64])
 @pytest.mark.parametrize("path", GOLDEN, ids=[os.path.basename(p) for p in GOLDEN])
-def test_crop_long_run_vs_oracle(path):
+def test_crop_long_run_vs_oracle(path, precision):
     gold = json.load(open(path))
     nx, ny = gold["Nx"], gold["Ny"]
-    print("\n[case] crop %dx%d, 50000 steps vs oracle record" % (nx, ny), flush=True)
+    print("\n[case] crop %dx%d precision %d, 50000 steps vs oracle record" % (nx, ny, precision),
+          flush=True)
     assert abs(configs.wall_fraction_for_angle(75.0) - gold["wall_fraction"]) < 1e-9
     p = configs.channel_params(nx, ny, 75.0, gold["Tw_over_Tc"], gold["g_osc"], gold["period"],
-                               lbm.LBM_FP32_DEV_MASSEXACT)
+                               precision)
     rho0 = inputs.density_field(nx, ny, p.rho_v, 0.01, gold["seed"])
     thr = 0.5 * (p.rho_l + p.rho_g)
     s = lbm.Sim(p, rho0)
@@ -50,16 +56,32 @@ def test_crop_long_run_vs_oracle(path):
             print(rec["step"], "gpu", st, "oracle", {k: rec[k] for k in ("bottom", "top",
                   "condensed_nodes")}, "profile errors rho %.2e T %.2e ux %.2e" % (e_rho, e_T, e_ux),
                   flush=True)
-            if rec["condensed_nodes"] == 0:
+            if precision == lbm.LBM_FP64:
+                # FP64 on both sides: rounding-level differences, which the
+                # nucleation and coalescence amplify (measured ~10x per 10000
+                # steps after step 20000) but which leave every droplet where
+                # the oracle has it
+                assert st["bottom"]["count"] == rec["bottom"]["count"]
+                assert st["top"]["count"] == rec["top"]["count"]
+                assert st["condensed_nodes"] == rec["condensed_nodes"]
+                assert e_rho < 1e-4 and e_T < 1e-6 and e_ux < 1e-4
+            elif rec["condensed_nodes"] == 0:
                 # metastable vapour: smooth fields, rounding-level agreement
                 assert st["condensed_nodes"] == 0
                 assert e_rho < 1e-3 and e_T < 1e-4 and e_ux < 1e-2
             else:
+                # FP32 storage: its rounding seeds a different droplet
+                # arrangement once the film breaks up (the process amplifies
+                # seeds, see the FP64 case), so only statistics compare: the
+                # droplet counts, the condensed volume, and the channel-mean
+                # temperature (near-plate T follows where droplets sit)
                 for side in ("bottom", "top"):
                     n_ref = rec[side]["count"]
-                    assert abs(st[side]["count"] - n_ref) <= max(1, round(0.3 * n_ref)), side
+                    assert abs(st[side]["count"] - n_ref) <= max(2, round(0.4 * n_ref)), side
                 c_ref = rec["condensed_nodes"]
-                assert abs(st["condensed_nodes"] - c_ref) <= 0.2 * c_ref
-                assert e_T < 1e-3
+                assert abs(st["condensed_nodes"] - c_ref) <= 0.1 * c_ref
+                mean_T = float(np.mean(prof["T"]))
+                ref_mean_T = float(np.mean(rec["T_profile"]))
+                assert abs(mean_T / ref_mean_T - 1) < 1e-2
     finally:
         s.close()

@@ -2,7 +2,8 @@
 
 * Edge grids: strips narrower than a wave, widths around the 54-column strip
   boundary, channels with a single or two fluid rows.
-* Flags: periodic box, single-phase flow with gravity, frozen temperature.
+* Flags: periodic box, single-phase flow with gravity, frozen temperature,
+  temperature held on the frame of the box, the frame as a reservoir.
 * Full sizes: the 2048 x 256 and 8192 x 512 channels started from a density
   field that repeats every 128 columns.  The step has no cross-node
   reduction, so every 128-column tile must stay bitwise identical, and one
@@ -50,13 +51,18 @@ def test_edge_grids_fp64(orc, Nx, Ny):
 
 
 @pytest.mark.parametrize("flags", [lbm.LBM_PERIODIC_Y, lbm.LBM_SINGLE_PHASE,
-                                   lbm.LBM_FREEZE_T, lbm.LBM_PERIODIC_Y | lbm.LBM_FREEZE_T])
+                                   lbm.LBM_FREEZE_T, lbm.LBM_PERIODIC_Y | lbm.LBM_FREEZE_T,
+                                   lbm.LBM_FRAME_T, lbm.LBM_FRAME_T | lbm.LBM_PERIODIC_Y,
+                                   lbm.LBM_FRAME_RHO,
+                                   lbm.LBM_FRAME_T | lbm.LBM_FRAME_RHO | lbm.LBM_PERIODIC_Y])
 @pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
 def test_flags_parity(orc, flags, precision):
     _case("flags=%d precision=%d 60x20" % (flags, precision))
     extra = {}
     if flags & lbm.LBM_SINGLE_PHASE:
         extra = dict(g_x=1e-5, g_y=-2e-6, rho_v=0.0)
+    if flags & lbm.LBM_FRAME_RHO:
+        extra = dict(rho_frame=0.3)
     p = configs.channel_params(60, 20, 120.0, 0.8, 1e-5, 100.0, precision, flags, **extra)
     rho0 = inputs.density_field(60, 20, p.rho_g, 0.01, 11)
     e = field_errors(_gpu(p, rho0, 60), _oracle(orc, p, rho0, 60),
@@ -183,3 +189,22 @@ def test_parity_2000_steps(orc, precision):
         assert e["rho"] < 1e-10 and e["u"] < 1e-8 and e["T"] < 1e-10
     else:
         assert e["rho"] < 1e-4 and e["u"] < 1e-3 and e["T"] < 1e-4
+
+
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+@pytest.mark.parametrize("flags", [0, lbm.LBM_PERIODIC_Y])
+def test_cs_eos_parity(orc, precision, flags):
+    """The Carnahan-Starling option (a = 1, b = 4, R = 1) on a 96 x 24 channel
+    (cold plates at 0.8 T_c, vapour noise), 100 steps against the oracle.  The
+    drive (1e-4, period 400: a quarter period at step 100) makes max |u|
+    ~6e-3, well above the FP32 velocity floor of the thin CS vapour
+    (rho_g = 0.034: an ulp of its stored deviations moves u by ~1e-9), since
+    u is compared relative to max |u|."""
+    _case("CS EOS 96x24 flags=%d precision=%d" % (flags, precision))
+    p = configs.channel_params_cs(96, 24, 0.45, 0.8, 1e-4, 400.0, precision, flags)
+    rho0 = configs.initial_density(p, seed=13)
+    e = field_errors(_gpu(p, rho0, 100), _oracle(orc, p, rho0, 100),
+                     fluid_mask(96, 24, bool(flags & lbm.LBM_PERIODIC_Y)))
+    print(e, flush=True)
+    tol = (1e-11, 1e-9, 1e-11) if precision == lbm.LBM_FP64 else (1e-5, 1e-5, 1e-5)
+    assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]

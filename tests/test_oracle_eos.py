@@ -111,3 +111,92 @@ def test_psi_clamps_only_past_dense_limit(orc):
     T = p.T0
     assert orc.psi(p, 8.9, T) > 0
     assert orc.psi(p, 9.05, T) == 0.0
+
+
+@pytest.mark.parametrize("frac", [0.56, 0.65, 0.78, 0.86, 0.95])
+def test_latent_heat_matches_clapeyron(orc, frac):
+    """Eq. 19 against the Clausius-Clapeyron relation
+    h_fg = T (dp_s/dT) (1/rho_g - 1/rho_l), with dp_s/dT from central
+    differences of the equal-area saturation pressure (an independent route:
+    it uses only the Maxwell construction, not the energy integral)."""
+    p = orc.default_params()
+    tc = orc.critical()[1]
+    T = frac * tc
+    h = orc.latent_heat(p, T)
+    dT = 1e-5 * T
+    ps_hi = orc.maxwell(p, T + dT)[2]
+    ps_lo = orc.maxwell(p, T - dT)[2]
+    g, l, _ = orc.maxwell(p, T)
+    h_cc = T * (ps_hi - ps_lo) / (2 * dT) * (1 / g - 1 / l)
+    assert h > 0
+    assert abs(h / h_cc - 1) < 1e-6
+
+
+def test_latent_heat_vanishes_at_critical_point(orc):
+    p = orc.default_params()
+    tc = orc.critical()[1]
+    h_far = orc.latent_heat(p, 0.6 * tc)
+    h_near = orc.latent_heat(p, 0.999 * tc)
+    assert 0 < h_near < 0.1 * h_far
+    with pytest.raises(ValueError):
+        orc.latent_heat(p, 1.01 * tc)
+
+
+def test_jacob_number(orc):
+    p = orc.default_params()
+    tc = orc.critical()[1]
+    ja = orc.jacob(p, 0.86 * tc, 0.65 * tc)
+    assert ja == pytest.approx(p.Cv * 0.21 * tc / orc.latent_heat(p, 0.86 * tc), rel=1e-15)
+
+
+# ---- Carnahan-Starling option ------------------------------------------------
+def test_cs_critical_point(orc):
+    """CS critical point (a = 1, b = 4, R = 1): dP/drho = d2P/drho2 = 0 there
+    (central differences of P, not the spinodal search), and T_c = 0.0943
+    as tabulated for this parameter set in the pseudopotential literature."""
+    rc, tc = orc.critical_cs()
+    p = orc.default_params_cs()
+    h = 1e-4 * rc
+    P = lambda r: orc.peos(p, r, tc)
+    d1 = (P(rc + h) - P(rc - h)) / (2 * h)
+    d2 = (P(rc + h) - 2 * P(rc) + P(rc - h)) / h ** 2
+    assert abs(d1) < 1e-9 and abs(d2) < 1e-4
+    assert tc == pytest.approx(0.0943, abs=5e-5)
+    assert 0.25 * 4 * rc == pytest.approx(0.1304, abs=5e-4)  # packing fraction
+
+
+def test_cs_derivatives_match_finite_differences(orc):
+    p = orc.default_params_cs()
+    for rho in (0.02, 0.13, 0.3, 0.5):
+        for frac in (0.6, 0.86, 1.0):
+            T = frac * p.Tc
+            hT, hr = 1e-6 * T, 1e-7
+            fdT = (orc.peos(p, rho, T + hT) - orc.peos(p, rho, T - hT)) / (2 * hT)
+            fdr = (orc.peos(p, rho + hr, T) - orc.peos(p, rho - hr, T)) / (2 * hr)
+            assert abs(orc.dpdT(p, rho, T) - fdT) < 1e-7 * max(1.0, abs(fdT))
+            assert abs(orc.dpdrho(p, rho, T) - fdr) < 1e-6 * max(1.0, abs(fdr))
+
+
+@pytest.mark.parametrize("frac", [0.6, 0.75, 0.86, 0.95])
+def test_cs_maxwell_equal_chemical_potential(orc, frac):
+    p = orc.default_params_cs()
+    T = frac * p.Tc
+    rg, rl, ps = orc.maxwell(p, T)
+    assert 0 < rg < rl < 1.0
+    dmu, _ = integrate.quad(lambda r: orc.dpdrho(p, r, T) / r, rg, rl, limit=400,
+                            epsrel=1e-12, points=[2 * rg, 0.1, 0.3])
+    scale, _ = integrate.quad(lambda r: abs(orc.dpdrho(p, r, T)) / r, rg, rl, limit=400)
+    assert abs(dmu) < 1e-9 * scale
+    assert orc.peos(p, rg, T) == pytest.approx(ps, rel=1e-10)
+    assert orc.peos(p, rl, T) == pytest.approx(ps, rel=1e-10)
+
+
+@pytest.mark.parametrize("frac", [0.6, 0.86])
+def test_cs_latent_heat_matches_clapeyron(orc, frac):
+    p = orc.default_params_cs()
+    T = frac * p.Tc
+    h = orc.latent_heat(p, T)
+    dT = 1e-5 * T
+    dps = (orc.maxwell(p, T + dT)[2] - orc.maxwell(p, T - dT)[2]) / (2 * dT)
+    g, l, _ = orc.maxwell(p, T)
+    assert h == pytest.approx(T * dps * (1 / g - 1 / l), rel=1e-6)

@@ -126,3 +126,94 @@ def test_rk4_advection_mode(orc):
     z = -1j * U * np.sin(k) + p.lam / (rho * p.Cv) * 2 * (np.cos(k) - 1)
     expect = p.T0 + np.real(-1j * eps * _rk4_factor(z) ** steps * np.exp(1j * k * x))
     np.testing.assert_allclose(T, expect, rtol=0, atol=1e-13 * p.T0)
+
+
+@pytest.mark.parametrize("k,l", [(1, 1), (2, 3)])
+def test_frame_held_box_mode_decay(orc, k, l):
+    """FRAME_T box at rest: the frame holds T_w, and a product of sines that
+    vanishes on the frame is an eigenvector of the nine-point Laplacian with
+    eigenvalue (4/3)(cos a + cos b - 2) + (2/3)(cos a cos b - 1), so the
+    coupled step multiplies it by R(z) exactly up to rounding."""
+    Nx, Ny, steps, rho = 12, 9, 30, 0.9
+    p = orc.default_params(Nx=Nx, Ny=Ny, period=0.0, lam=0.3, Cv=1.7,
+                           flags=orc.PERIODIC_Y | orc.SINGLE_PHASE | orc.FRAME_T)
+    p.Tw = 0.9 * orc.critical()[1]
+    s = orc.Sim(p, rho_uniform=rho)
+    x, y = _grid(Nx, Ny)
+    a, b = k * np.pi / (Nx - 1), l * np.pi / (Ny - 1)
+    eps = 1e-3 * p.Tw
+    mode = np.sin(a * x) * np.sin(b * y)
+    s.set_T(p.Tw + eps * mode)
+    s.step(steps)
+    T = s.moments()[3]
+    lam9 = 4 / 3 * (np.cos(a) + np.cos(b) - 2) + 2 / 3 * (np.cos(a) * np.cos(b) - 1)
+    z = p.lam / (rho * p.Cv) * lam9
+    np.testing.assert_allclose(T, p.Tw + eps * _rk4_factor(z) ** steps * mode, rtol=0,
+                               atol=1e-13 * p.Tw)
+
+
+def test_frame_temperature_held_with_flow(orc):
+    """A two-phase box with FRAME_T: the frame nodes keep T_w exactly while
+    the interior evolves; without the flag the frame nodes move."""
+    Nx, Ny = 16, 12
+    tc = orc.critical()[1]
+    p = orc.default_params(Nx=Nx, Ny=Ny, period=0.0, flags=orc.PERIODIC_Y | orc.FRAME_T)
+    p.Tw = tc
+    x, y = _grid(Nx, Ny)
+    r = np.hypot(x - Nx / 2, y - Ny / 2)
+    rho0 = 0.5 * (p.rho_l + p.rho_g) - 0.5 * (p.rho_l - p.rho_g) * np.tanh(2 * (r - 4) / 3)
+    s = orc.Sim(p, rho0)
+    s.step(20)
+    T = s.moments()[3]
+    frame = np.zeros((Ny, Nx), dtype=bool)
+    frame[0] = frame[-1] = True
+    frame[:, 0] = frame[:, -1] = True
+    assert np.all(T[frame] == p.Tw)
+    assert np.abs(T[~frame] - p.T0).max() > 1e-6
+    q = orc.default_params(Nx=Nx, Ny=Ny, period=0.0, flags=orc.PERIODIC_Y)
+    q.Tw = tc
+    s2 = orc.Sim(q, rho0)
+    s2.step(20)
+    assert np.abs(s2.moments()[3][frame] - p.Tw).min() > 1e-3 * tc
+
+
+def test_reservoir_frame_uniform_equilibrium(orc):
+    """FRAME_RHO | FRAME_T box whose interior already matches the reservoir
+    (rho = rho_frame, T = T_w, at rest): nothing moves, with the two-phase
+    EOS and forces on (uniform psi gives no force)."""
+    Nx, Ny = 10, 8
+    tc = orc.critical()[1]
+    p = orc.default_params(Nx=Nx, Ny=Ny, period=0.0,
+                           flags=orc.PERIODIC_Y | orc.FRAME_T | orc.FRAME_RHO)
+    p.Tw = p.T0 = 0.9 * tc
+    p.rho_frame = 0.3
+    s = orc.Sim(p, rho_uniform=0.3)
+    s.step(25)
+    rho, ux, uy, T, _, _ = s.moments()
+    np.testing.assert_allclose(rho, 0.3, rtol=1e-14)
+    assert np.abs(ux).max() < 1e-15 and np.abs(uy).max() < 1e-15
+    np.testing.assert_allclose(T, p.Tw, rtol=1e-14)
+
+
+def test_reservoir_frame_values_held(orc):
+    """A droplet in a FRAME_RHO | FRAME_T box: the frame keeps rho_frame,
+    u = 0 and T_w exactly; mass leaves or enters through it (the interior
+    vapour starts at rho_g, the reservoir is thinner)."""
+    Nx, Ny = 18, 14
+    tc = orc.critical()[1]
+    p = orc.default_params(Nx=Nx, Ny=Ny, period=0.0,
+                           flags=orc.PERIODIC_Y | orc.FRAME_T | orc.FRAME_RHO)
+    p.Tw = tc
+    p.rho_frame = 0.29
+    x, y = _grid(Nx, Ny)
+    r = np.hypot(x - (Nx - 1) / 2, y - (Ny - 1) / 2)
+    rho0 = 0.5 * (p.rho_l + p.rho_g) - 0.5 * (p.rho_l - p.rho_g) * np.tanh(2 * (r - 4) / 3)
+    s = orc.Sim(p, rho0)
+    s.step(30)
+    rho, ux, uy, T, _, _ = s.moments()
+    frame = np.zeros((Ny, Nx), dtype=bool)
+    frame[0] = frame[-1] = True
+    frame[:, 0] = frame[:, -1] = True
+    assert np.all(rho[frame] == 0.29) and np.all(ux[frame] == 0) and np.all(uy[frame] == 0)
+    assert np.all(T[frame] == p.Tw)
+    assert abs(rho[~frame].sum() - rho0[~frame].sum()) > 1e-6 * rho0.sum()
