@@ -617,19 +617,38 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         dst.T = bload(rb, vx, B.Tin + (unsigned)rS.sr * rowb, S(0));
         dst.lo = kMX ? bload(rb, vlo, B.lo_in + (unsigned)rS.sr * rowb_lo, 0.0f) : 0.0f;
     };
+    // the loads of an interior row (plate-free neighbours, no wrap in y)
+    auto issue_loads_interior = [&](const int y, RawRow& dst) {
+        const RowK rL{true, false, false, y - 1};
+        pull_row_buf<S>(rb, g, rL, B.fin, vx, vm, vp, dst.d);
+        dst.T = bload(rb, vx, B.Tin + (unsigned)rL.sr * rowb, S(0));
+        dst.lo = kMX ? bload(rb, vlo, B.lo_in + (unsigned)rL.sr * rowb_lo, 0.0f) : 0.0f;
+    };
     if (kAhead) {
         issue_loads(ya - kHalo, raw);
         cur = raw;
     }
-    auto row_iteration = [&](const int kr) {
+    // A row iteration in two builds.  The general one (kFast false) handles
+    // every case.  The interior one serves the steady state of a segment in
+    // the common configuration (plates, temperature on, two phases, no
+    // optional feature): every stage is active, all six rows are fluid rows
+    // off the plates and the two stores are owned, so it has no branch but
+    // the lane masks of the stores, which lets the scheduler interleave the
+    // stages.
+    auto row_interior = [&](const int kr, const int j) { return RowK{true, false, false, kr - j - 1}; };
+    auto row_iteration = [&](const int kr, auto fast_tag) {
+        constexpr bool kFast = decltype(fast_tag)::value;
         // Padding iterations past kr_end compute and store nothing.
-        const bool live = kr < kr_end;
-        if (kAhead) issue_loads(kr + 1, raw);
+        const bool live = kFast || kr < kr_end;
+        if (kAhead) {
+            if (kFast) issue_loads_interior(kr + 1, raw);
+            else issue_loads(kr + 1, raw);
+        }
         // ------------- stage A: row kr: pull, rho, j, psi -----------------
-        const RowK rA = row_info(kr, g);
+        const RowK rA = kFast ? row_interior(kr, 0) : row_info(kr, g);
         Tri<double> psiA;
         R dTA;
-        if (rA.fluid && live) {
+        if (kFast || (rA.fluid && live)) {
             if (!kAhead) issue_loads(kr, cur);
             const S rawT = cur.T;
             const R lo = kMX ? (R)cur.lo : (R)0;
@@ -673,17 +692,19 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         // skipped (the first iterations of a segment): B needs rows from
         // ya-4, C from ya-3, D from ya-2, E from ya-1 (each stage widens the
         // stencil by one row); their window entries are then never read.
-        const bool needB = live && kr - 1 >= ya - 4, needC = live && kr - 2 >= ya - 3;
-        const bool needD = live && kr - 3 >= ya - 2, needE = live && kr - 4 >= ya - 1;
+        const bool needB = kFast || (live && kr - 1 >= ya - 4);
+        const bool needC = kFast || (live && kr - 2 >= ya - 3);
+        const bool needD = kFast || (live && kr - 3 >= ya - 2);
+        const bool needE = kFast || (live && kr - 4 >= ya - 1);
         // ------------- stage B: forces, u, collision on row kr-1 ---------
-        const RowK rB = row_info(kr - 1, g);
+        const RowK rB = kFast ? row_interior(kr, 1) : row_info(kr - 1, g);
         Tri<R> uxB, uyB;
-        if (rB.fluid && needB) {
+        if (kFast || (rB.fluid && needB)) {
             double Fxd = 0.0, Fyd = 0.0, Fmx = 0.0, Fmy = 0.0;
-            if (!single) {
+            if (kFast || !single) {
                 pair_force(psi2, psi1, psi0, k.negG, Fxd, Fyd);
                 Fmx = Fxd;
-                Fmy = Fyd - wall_adhesion_y(rB, psi1.c, k);
+                Fmy = kFast ? Fyd : Fyd - wall_adhesion_y(rB, psi1.c, k);
             } else {
                 Fyd = wall_adhesion_y(rB, psi1.c, k);
             }
@@ -697,10 +718,10 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             if (resB) ux = uy = 0;
             uxB = tri<R>(ux);
             uyB = tri<R>(uy);
-            if (kr - 1 >= ya && kr - 1 < yb) {
+            if (kFast || (kr - 1 >= ya && kr - 1 < yb)) {
                 // Eq. 8 theta term uses |F_m|^2 / psi^2 of the fluid-fluid force
                 R th = 0;
-                if (!single && psi1.c > 0.0)
+                if ((kFast || !single) && psi1.c > 0.0)
                     th = (R)((Fmx * Fmx + Fmy * Fmy) * rcp_d<sizeof(S) == 4 ? 1 : 2>(psi1.c * psi1.c));
                 // Eq. 5 with a clamped fraction
                 R fr = (rho - kr_.rho_g) * kr_.inv_drho;
@@ -742,11 +763,11 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         ux1 = uxB;
         uy1 = uyB;
 
-        if (!freezeT) {
+        if (kFast || !freezeT) {
             // ------------- stage C: div u, coefficients, h1 on row kr-2 ---
-            const RowK rC = row_info(kr - 2, g);
+            const RowK rC = kFast ? row_interior(kr, 2) : row_info(kr - 2, g);
             Tri<R> t1;
-            if (rC.fluid && needC) {
+            if (kFast || (rC.fluid && needC)) {
                 const R dv = div_u<R>(ux3, ux2, ux1, uy3, uy2, uy1);
                 cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, cv, eos_cs);
                 R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
@@ -759,9 +780,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             }
             t1a = t1;
             // ------------- stage D: h2 on row kr-3 ------------------------
-            const RowK rD = row_info(kr - 3, g);
+            const RowK rD = kFast ? row_interior(kr, 3) : row_info(kr - 3, g);
             Tri<R> t2;
-            if (rD.fluid && needD) {
+            if (kFast || (rD.fluid && needD)) {
                 R h2 = heat_rhs<R>(t1c, t1b, t1a, cf3, T_ref);
                 if (held(rD)) h2 = 0;
                 acc3 += (R)2 * h2;
@@ -771,9 +792,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             }
             t2a = t2;
             // ------------- stage E: h3 on row kr-4 ------------------------
-            const RowK rE = row_info(kr - 4, g);
+            const RowK rE = kFast ? row_interior(kr, 4) : row_info(kr - 4, g);
             Tri<R> t3;
-            if (rE.fluid && needE) {
+            if (kFast || (rE.fluid && needE)) {
                 R h3 = heat_rhs<R>(t2c, t2b, t2a, cf4, T_ref);
                 if (held(rE)) h3 = 0;
                 acc4 += (R)2 * h3;
@@ -790,9 +811,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             cur.T = settle(raw.T);
             if (kMX) cur.lo = settle(raw.lo);
         }
-        if (!freezeT) {
-            const RowK rF = row_info(kr - 5, g);
-            if (rF.fluid && kr - 5 >= ya && kr - 5 < yb) {
+        if (kFast || !freezeT) {
+            const RowK rF = kFast ? row_interior(kr, 5) : row_info(kr - 5, g);
+            if (kFast || (rF.fluid && kr - 5 >= ya && kr - 5 < yb)) {
                 R h4 = heat_rhs<R>(t3c, t3b, t3a, cf5, T_ref);
                 if (held(rF)) h4 = 0;
                 const R tnew = tn5 + (acc5 + h4) * ((R)1 / 6);
@@ -834,13 +855,26 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         for (int q = 0; q < 9; ++q) dPrv[q] = dCur[q];
 
     };
+    // interior iterations: kr - 5 .. kr + 1 inside the segment's owned rows
+    // and the stages' reach, all rows at least two rows off the plates
+    const bool fast_ok = !kExt && !freezeT && !single && !g.periodic_y;
+    const int fast_lo = max(ya + kHalo, 6), fast_hi = min(yb, g.Ny - 4);
+    auto step_row = [&](const int kr) {
+        if constexpr (!kExt) {
+            if (fast_ok && kr >= fast_lo && kr <= fast_hi) {
+                row_iteration(kr, std::true_type{});
+                return;
+            }
+        }
+        row_iteration(kr, std::false_type{});
+    };
     for (int kr = ya - kHalo; kr < kr_end; kr += 6) {
-        row_iteration(kr);
-        row_iteration(kr + 1);
-        row_iteration(kr + 2);
-        row_iteration(kr + 3);
-        row_iteration(kr + 4);
-        row_iteration(kr + 5);
+        step_row(kr);
+        step_row(kr + 1);
+        step_row(kr + 2);
+        step_row(kr + 3);
+        step_row(kr + 4);
+        step_row(kr + 5);
     }
 }
 
@@ -851,8 +885,12 @@ __device__ __forceinline__ int wave_in_block() {
 
 // The FP64 build has its own kernel: it needs about 256 registers and runs
 // one wave per SIMD, the FP32 builds fit three.
+// Register budgets: three waves per SIMD for the FP32 builds (168 VGPRs), two
+// for the FP64 build (256); the interior path would otherwise take a few
+// more registers than that and lose a resident wave.
 template <class S, bool kMX, bool kExt>
-__global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Phys k, Bufs<S> B,
+__global__ __launch_bounds__(kLanes* kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(3)))
+void step_kernel(Grid g, Phys k, Bufs<S> B,
                                                                         long long n) {
     const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
     if (unit >= g.n_units) return;  // whole waves only
@@ -860,7 +898,8 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel(Grid g, Ph
 }
 
 template <bool kExt>
-__global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel_f64(Grid g, Phys k,
+__global__ __launch_bounds__(kLanes* kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void step_kernel_f64(Grid g, Phys k,
                                                                         Bufs<double> B,
                                                                         long long n) {
     const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
@@ -871,7 +910,8 @@ __global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_kernel_f64(Grid g
 // Step i of a chunk over a batch of channels.  The slot of a unit is found by
 // a binary search over the slots' first units (wave-uniform).
 template <bool kExt>
-__global__ __launch_bounds__(kLanes* kWavesPerBlock) void step_batched_kernel(
+__global__ __launch_bounds__(kLanes* kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(3)))
+void step_batched_kernel(
     const Slot* __restrict__ slots, int n_slots, int total_units, int nblocks_pad, int step_i) {
     const int unit = unit_of_block(nblocks_pad) * kWavesPerBlock + wave_in_block();
     if (unit >= total_units) return;
