@@ -252,6 +252,41 @@ def d2_law_study(N=200, D=60.0, max_steps=320000, every=4000):
     return out
 
 
+def open_channel_run(steps=6000, every=2000):
+    """Sec. 3.3 boundary set on the paper's 1600 x 48 channel (Zou-He
+    oscillating-pressure inlet, constant-pressure outlet, plates 0.86 -> 0.56
+    T_c, gravity +x, 137.82 degree plates), FP32: throughput and the
+    condensate (liquid nodes, droplets on the plates) every `every` steps.
+    The run stops at 6000 steps: with the outlet held at the saturation
+    pressure of 0.86 T_c, the vapour entering at the cold outlet corners
+    reaches |u| ~ 0.3 and the state turns non-finite between steps 6000 and
+    8000 (FP32 and FP64 alike, and the oracle on a shortened channel)."""
+    from paper_1803_01756_amd import analysis, configs, lbm
+    p = configs.open_channel()
+    s = lbm.Sim(p, configs.initial_density(p, seed=1))
+    s.autotune(3)
+    out = dict(steps=steps, samples=[])
+    s.synchronize()
+    t0 = time.perf_counter()
+    dt_steps = 0.0
+    while s.n < steps:
+        t1 = time.perf_counter()
+        s.step(every)
+        s.synchronize()
+        dt_steps += time.perf_counter() - t1
+        rho = s.moments()[0]
+        thr = 0.5 * (p.rho_l + p.rho_g)
+        d = analysis.droplets(rho, thr)
+        out["samples"].append(dict(step=int(s.n), liquid_nodes=int((rho[1:-1] > thr).sum()),
+                                   droplets_bottom=d["bottom"]["count"],
+                                   droplets_top=d["top"]["count"],
+                                   liquid_nodes_x_gt_1500=int((rho[1:-1, 1500:] > thr).sum())))
+    out["mlups"] = round(fluid_nodes(p) * steps / dt_steps / 1e6, 1)
+    s.close()
+    log("open channel 1600x48: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +355,7 @@ def main():
         extra["precision_2048x256"] = precision_study()
         extra["mass_run_8192x512"] = large_mass_run()
         extra["d2_law_200x200"] = d2_law_study()
+        extra["open_channel_1600x48"] = open_channel_run()
 
     batched = served = None
     if not args.no_batch:

@@ -73,10 +73,20 @@ enum {
                               post-collision populations are the rest
                               equilibrium of rho_frame (mass is then not
                               conserved: vapour leaves or enters)            */
-    LBM_EOS_CS = 32u       /* Carnahan-Starling EOS in place of Eq. 11:
+    LBM_EOS_CS = 32u,      /* Carnahan-Starling EOS in place of Eq. 11:
                               P = rho R T (1 + e + e^2 - e^3) / (1 - e)^3
                               - a rho^2, e = b rho / 4 (usual constants
                               a = 1, b = 4, R = 1); omega is then unused   */
+    LBM_OPEN_X = 64u       /* Sec. 3.3 boundary set: x is not periodic;
+                              column 0 is a Zou-He pressure inlet, column
+                              Nx-1 a Zou-He pressure outlet (zero transverse
+                              velocity).  Pressures are EOS pressures:
+                              p_in(n) = p0 (1 + p_amp sin(2 pi n / p_period))
+                              (p_period <= 0: p0 (1 + p_amp)), p_out = p0,
+                              p0 = P_EOS(rho_v, T_in); the boundary densities
+                              are their vapour-branch roots.  Stencils past
+                              the ends see the boundary column's own values;
+                              the inlet column holds T = T_in.              */
 };
 
 /* Parameters, named as in the paper.  lbm_params_default() fills the paper's
@@ -100,9 +110,14 @@ typedef struct {
     double rho_ref;         /* density of the stored deviations; <= 0: rho_v (or
                                the Maxwell gas density when rho_v is 0)          */
     double rho_frame;       /* LBM_FRAME_RHO reservoir density (> 0 required)   */
+    double p_amp, p_period; /* LBM_OPEN_X inlet pressure oscillation             */
+    double T_w_end;         /* > 0: plate temperature linear in x, from T_w at
+                               x = 0 to T_w_end at x = Nx-1 (Sec. 3.3)          */
+    double T_in;            /* LBM_OPEN_X inlet temperature; <= 0: T_0          */
     int32_t precision;      /* LBM_FP32_DEV, LBM_FP64 or LBM_FP32_DEV_MASSEXACT   */
     uint32_t flags;         /* LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y |
-                               LBM_FRAME_T | LBM_FRAME_RHO                       */
+                               LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS |
+                               LBM_OPEN_X                                        */
 } lbm_params;
 
 /* Fill *p with the defaults: Nx = 128, Ny = 32, a = 3/49, b = 2/21, R = 1,

@@ -51,6 +51,17 @@
  *    post-collision populations are the rest equilibrium of rho_frame, so
  *    evaporated vapour can leave the box (a closed box only heats up and
  *    compresses its vapour).
+ *  - Sec. 3.3 (flag OPEN_X): x is not periodic.  Column 0 is a Zou-He
+ *    pressure inlet, column Nx-1 a Zou-He pressure outlet (zero transverse
+ *    velocity); "pressure" is the EOS pressure, so the prescribed densities
+ *    solve P_EOS(rho, T_in) = p on the vapour branch, with
+ *    p_in(n) = p0 (1 + p_amp sin(2 pi n / p_period)), p_out = p0 and
+ *    p0 = P_EOS(rho_v, T_in).  The unknown populations of a boundary column
+ *    are rebuilt from the known ones at the start of each step (time level
+ *    n).  Stencils that reach past x = 0 or x = Nx-1 see a zero-gradient
+ *    ghost (the boundary column's own psi, T, u).  The inlet column holds
+ *    T = T_in; the outlet's T evolves.  With Tw_end > 0 the plates'
+ *    temperature varies linearly from Tw at x = 0 to Tw_end at x = Nx-1.
  */
 #define _USE_MATH_DEFINES
 #include <math.h>
@@ -67,6 +78,7 @@
 #define ORC_FRAME_RHO 16u   /* the same frame is a reservoir at rest with   */
                             /* density rho_frame                            */
 #define ORC_EOS_CS 32u      /* Carnahan-Starling EOS in place of Eq. 11     */
+#define ORC_OPEN_X 64u      /* Zou-He pressure inlet / outlet in x          */
 
 typedef struct {
     int32_t Nx, Ny;
@@ -80,6 +92,8 @@ typedef struct {
     double g_osc, period;         /* oscillating drive along +x */
     double gx, gy, rho_v;         /* Eq. 15 */
     double rho_frame;             /* FRAME_RHO reservoir density */
+    double p_amp, p_period;       /* OPEN_X inlet pressure oscillation */
+    double Tw_end, T_in;          /* plate T at x = Nx-1 (<= 0: uniform); inlet T (<= 0: T0) */
     uint32_t flags;
     int32_t pad_;
 } orc_params;
@@ -410,15 +424,28 @@ static int on_frame(const orc_params* p, int x, int y) {
     if (x == 0 || x == p->Nx - 1) return 1;
     return (p->flags & ORC_PERIODIC_Y) && (y == 0 || y == p->Ny - 1);
 }
-/* nodes whose temperature is a boundary value: the plates and a FRAME_T frame */
+/* nodes whose temperature is a boundary value: the plates, a FRAME_T frame
+ * and an OPEN_X inlet column */
 static int t_held(const orc_params* p, int x, int y) {
     if (is_solid(p, y)) return 1;
+    if ((p->flags & ORC_OPEN_X) && x == 0) return 1;
     return (p->flags & ORC_FRAME_T) && on_frame(p, x, y);
 }
 /* reservoir nodes of a FRAME_RHO frame */
 static int reservoir(const orc_params* p, int x, int y) {
     return (p->flags & ORC_FRAME_RHO) && !is_solid(p, y) && on_frame(p, x, y);
 }
+/* x neighbour: periodic, or with OPEN_X the clamped column (zero-gradient
+ * ghost) */
+static int nbx(const orc_params* p, int x) {
+    if (p->flags & ORC_OPEN_X) return x < 0 ? 0 : (x >= p->Nx ? p->Nx - 1 : x);
+    return wrapx(p, x);
+}
+static double tw_at(const orc_params* p, int x) {
+    if (!(p->Tw_end > 0.0) || p->Nx < 2) return p->Tw;
+    return p->Tw + (p->Tw_end - p->Tw) * (double)x / (double)(p->Nx - 1);
+}
+static double t_inlet(const orc_params* p) { return p->T_in > 0.0 ? p->T_in : p->T0; }
 static int wrapy(const orc_params* p, int y) {
     if (p->flags & ORC_PERIODIC_Y) return (y % p->Ny + p->Ny) % p->Ny;
     return y; /* fluid rows 1..Ny-2 never reach past rows 0 and Ny-1 */
@@ -468,7 +495,9 @@ void orc_sim_init(orc_sim* s, const double* rho0, double rho_uniform) {
                 feq[i] = v;
             }
             for (int i = 0; i < 9; ++i) s->f[FIDX(p, i, x, y)] = is_solid(p, y) ? 0.0 : feq[i];
-            s->T[IDX(p, x, y)] = t_held(p, x, y) ? p->Tw : p->T0;
+            double Tb = is_solid(p, y) ? tw_at(p, x) : p->Tw;
+            if ((p->flags & ORC_OPEN_X) && x == 0 && !is_solid(p, y)) Tb = t_inlet(p);
+            s->T[IDX(p, x, y)] = t_held(p, x, y) ? Tb : p->T0;
         }
 }
 void orc_sim_set_f(orc_sim* s, const double* f) {
@@ -483,6 +512,59 @@ void orc_sim_set_T(orc_sim* s, const double* T) {
 void orc_sim_set_time(orc_sim* s, int64_t n) { s->n = n; }
 int64_t orc_sim_time(const orc_sim* s) { return s->n; }
 int64_t orc_sim_psi_clamps(const orc_sim* s) { return s->psi_clamps; }
+
+/* OPEN_X boundary densities.  Inlet: the vapour-branch root of
+ * P_EOS(rho, T_in) = p0 (1 + p_amp sin(2 pi n / p_period)) (p_period <= 0:
+ * the constant p0 (1 + p_amp)), by bisection below the vapour spinodal (the
+ * first zero of dP/drho); outlet: rho_v. */
+double orc_inlet_density(const orc_params* p, int64_t n) {
+    const double T = t_inlet(p);
+    const double p0 = orc_peos(p, p->rho_v, T);
+    const double target = p->p_period > 0.0
+        ? p0 * (1.0 + p->p_amp * sin(2.0 * 3.14159265358979323846 * (double)n / p->p_period))
+        : p0 * (1.0 + p->p_amp);
+    const double rmax = (p->flags & ORC_EOS_CS) ? 4.0 / p->b : 1.0 / p->b;
+    double hi = rmax * (1.0 - 1e-9);
+    const int m = 20000; /* scan for the vapour spinodal, if any */
+    for (int k = 1; k < m; ++k) {
+        double r = rmax * k / m;
+        if (orc_dpdrho(p, r, T) <= 0.0) { hi = r; break; }
+    }
+    double lo = 1e-12;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (orc_peos(p, mid, T) < target) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Zou-He reconstruction of the populations entering through an open end
+ * (zero transverse velocity, prescribed density), on the fluid rows of
+ * columns 0 (inlet) and Nx-1 (outlet), at time level n.  The corner nodes
+ * (end-column nodes next to a plate) take the velocity form with u = 0
+ * instead: they touch a no-slip wall, and a prescribed density there drives
+ * a jet along the plate. */
+static void open_ends(orc_sim* s) {
+    const orc_params* p = &s->p;
+    const double rin = orc_inlet_density(p, s->n), rout = p->rho_v;
+    const int xl = p->Nx - 1;
+    for (int y = 0; y < p->Ny; ++y) {
+        if (is_solid(p, y)) continue;
+        const int corner = !(p->flags & ORC_PERIODIC_Y) && (y == 1 || y == p->Ny - 2);
+        double* f[9];
+        for (int i = 0; i < 9; ++i) f[i] = &s->f[FIDX(p, i, 0, y)];
+        double j = corner ? 0.0
+                          : rin - (*f[0] + *f[2] + *f[4] + 2.0 * (*f[3] + *f[6] + *f[7]));
+        *f[1] = *f[3] + 2.0 / 3.0 * j;
+        *f[5] = *f[7] - 0.5 * (*f[2] - *f[4]) + j / 6.0;
+        *f[8] = *f[6] + 0.5 * (*f[2] - *f[4]) + j / 6.0;
+        for (int i = 0; i < 9; ++i) f[i] = &s->f[FIDX(p, i, xl, y)];
+        j = corner ? 0.0 : (*f[0] + *f[2] + *f[4] + 2.0 * (*f[1] + *f[5] + *f[8])) - rout;
+        *f[3] = *f[1] - 2.0 / 3.0 * j;
+        *f[7] = *f[5] + 0.5 * (*f[2] - *f[4]) - j / 6.0;
+        *f[6] = *f[8] - 0.5 * (*f[2] - *f[4]) - j / 6.0;
+    }
+}
 
 /* S1-S4: rho, psi, forces and the half-force velocity at time level n */
 static void macroscopic(orc_sim* s) {
@@ -514,7 +596,7 @@ static void macroscopic(orc_sim* s) {
             }
             double sfx = 0.0, sfy = 0.0, swx = 0.0, swy = 0.0;
             for (int i = 1; i < 9; ++i) {
-                int xn = wrapx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
+                int xn = nbx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
                 if (is_solid(p, yn)) {
                     swx += wgt(i) * EX[i];
                     swy += wgt(i) * EY[i];
@@ -559,7 +641,7 @@ static void heat_rhs(const orc_sim* s, const double* Ts, double* out) {
             if (is_solid(p, y)) { out[c] = 0.0; continue; }
             double tx = 0.0, ty = 0.0, lap = 0.0, div = 0.0;
             for (int i = 1; i < 9; ++i) {
-                int xn = wrapx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
+                int xn = nbx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
                 size_t cn = IDX(p, xn, yn);
                 double w = wgt(i);
                 tx += w * EX[i] * Ts[cn];
@@ -593,6 +675,7 @@ static void step_once(orc_sim* s) {
     const orc_params* p = &s->p;
     const int Nx = p->Nx, Ny = p->Ny;
     const size_t N = (size_t)Nx * Ny;
+    if (p->flags & ORC_OPEN_X) open_ends(s); /* S0: open ends at level n */
     macroscopic(s);
     /* S5-S6: collision on every fluid node into fpost */
     for (int y = 0; y < Ny; ++y)
@@ -647,9 +730,10 @@ static void step_once(orc_sim* s) {
         for (int x = 0; x < Nx; ++x) {
             if (is_solid(p, y)) continue;
             for (int i = 0; i < 9; ++i) {
-                int xn = wrapx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
+                int xr = x + EX[i], xn = wrapx(p, xr), yn = wrapy(p, y + EY[i]);
                 double v = s->fpost[FIDX(p, i, x, y)];
                 if (is_solid(p, yn)) s->f[FIDX(p, OPP[i], x, y)] = v;
+                else if ((p->flags & ORC_OPEN_X) && (xr < 0 || xr >= Nx)) continue; /* leaves */
                 else s->f[FIDX(p, i, xn, yn)] = v;
             }
         }
@@ -666,6 +750,7 @@ void orc_sim_step(orc_sim* s, int64_t nsteps) {
 void orc_sim_moments(orc_sim* s, double* rho, double* ux, double* uy, double* T, double* Fx,
                      double* Fy) {
     int64_t save = s->psi_clamps;
+    if (s->p.flags & ORC_OPEN_X) open_ends(s);
     macroscopic(s);
     s->psi_clamps = save;
     size_t N = (size_t)s->p.Nx * s->p.Ny;

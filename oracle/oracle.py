@@ -26,6 +26,7 @@ PERIODIC_Y = 4
 FRAME_T = 8
 FRAME_RHO = 16
 EOS_CS = 32
+OPEN_X = 64
 
 
 def build(force: bool = False) -> str:
@@ -54,6 +55,8 @@ class OrcParams(C.Structure):
         ("g_osc", C.c_double), ("period", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("rho_v", C.c_double),
         ("rho_frame", C.c_double),
+        ("p_amp", C.c_double), ("p_period", C.c_double),
+        ("Tw_end", C.c_double), ("T_in", C.c_double),
         ("flags", C.c_uint32), ("pad_", C.c_int32),
     ]
 
@@ -80,6 +83,8 @@ def lib():
         L.orc_maxwell.argtypes = [P, C.c_double, dp, dp, dp]
         L.orc_maxwell.restype = C.c_int
         L.orc_latent_heat.argtypes = [P, C.c_double, dp]
+        L.orc_inlet_density.argtypes = [P, C.c_int64]
+        L.orc_inlet_density.restype = C.c_double
         L.orc_latent_heat.restype = C.c_int
         L.orc_collide_node.argtypes = [P, dp] + [C.c_double] * 9 + [dp]
         L.orc_heat_rhs.argtypes = [P, dp, dp, dp, dp, dp]
@@ -169,6 +174,12 @@ def latent_heat(p: OrcParams, T: float) -> float:
     if lib().orc_latent_heat(C.byref(p), T, C.byref(h)) != 0:
         raise ValueError("temperature %g is not below the critical point" % T)
     return h.value
+
+
+def inlet_density(p: OrcParams, n: int) -> float:
+    """OPEN_X inlet density at time level n (vapour-branch root of the
+    oscillating inlet pressure)."""
+    return lib().orc_inlet_density(C.byref(p), n)
 
 
 def jacob(p: OrcParams, T_sat: float, T_w: float) -> float:

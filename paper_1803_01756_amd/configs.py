@@ -129,3 +129,28 @@ def droplet_density(p: lbm.lbm_params, D: float, width: float = 5.0) -> np.ndarr
     """A disc of diameter D at the box centre: tanh profile of the given width
     between the coexistence densities rho_l (inside) and rho_g."""
     return inputs.droplet_disc(p.Nx, p.Ny, D, p.rho_l, p.rho_g, width)
+
+
+def open_channel(Nx: int = 1600, Ny: int = 48, contact_angle: float = 137.82,
+                 p_amp: float = 0.1, p_period: float = 2000.0, g_x: float = 1e-4,
+                 precision=lbm.LBM_FP32_DEV, **overrides) -> lbm.lbm_params:
+    """Sec. 3.3: saturated vapour driven through a plate channel by an
+    oscillating inlet pressure p0 (1 + 0.1 sin(2 pi n / p_period)) against a
+    constant outlet pressure p0 (Zou-He ends, flag OPEN_X); plates at a
+    temperature falling linearly from 0.86 T_c at the inlet to 0.56 T_c at the
+    outlet; inlet vapour at T_sat = 0.86 T_c; gravity g_x = 1e-4 along +x; the
+    paper's hydrophobic plates (137.82 degrees).  The oscillation frequency is
+    not given, so p_period is a parameter."""
+    p = lbm.lbm_params_default(Nx=Nx, Ny=Ny, g_osc=0.0, period=0.0, precision=precision,
+                               flags=lbm.LBM_OPEN_X)
+    p = lbm.lbm_params_resolve(p)
+    p.T_w = 0.86 * p.T_c
+    p.T_w_end = 0.56 * p.T_c
+    p.T_in = p.T_0
+    p.p_amp, p.p_period, p.g_x = p_amp, p_period, g_x
+    frac = wall_fraction_for_angle(contact_angle)
+    p.G_w = p.G
+    p.psi_w = lbm.lbm_eos_pressure(p, p.rho_g + frac * (p.rho_l - p.rho_g), p.T_0)[1]
+    for k, v in overrides.items():
+        setattr(p, "lambda_" if k == "lambda" else k, v)
+    return p

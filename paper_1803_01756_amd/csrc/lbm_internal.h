@@ -41,6 +41,12 @@ struct Phys {
     double g_osc, period;               // drive g_osc sin(2 pi n / period) along +x
     double g_x, g_y, rho_v;             // Eq. 15
     double rho_frame;                   // reservoir density of a frame
+    double p0, p_amp, p_period;         // open ends: inlet pressure p0 (1 + p_amp sin(...))
+    double T_in_eos;                    // temperature of the boundary EOS pressures
+    double rho_sp;                      // vapour spinodal density at T_in_eos (bracket)
+    double dT_in;                       // inlet temperature - T_ref
+    double dT_w_end;                    // plate temperature at x = Nx-1 - T_ref
+    int wall_ramp;                      // plate temperature linear in x
     double rkA, rkB1, rkB2;             // R, a k (1+k)/sqrt(Tc), a k^2 / Tc
     uint32_t flags;                     // LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y
     uint32_t pad_;
@@ -56,6 +62,7 @@ struct Grid {
     int periodic_y;
     int frame_t;       // T held at T_w on the frame: outermost columns (and rows if periodic_y)
     int frame_rho;     // the frame is a reservoir at rest with density rho_frame
+    int open_x;        // Zou-He pressure inlet at x = 0, outlet at x = Nx-1
     int n_strips, n_segs, seg_rows, n_units, n_blocks_pad;
     unsigned plane;    // rows * pitch
 };

@@ -474,6 +474,65 @@ struct RealOf<double> {
     using T = double;
 };
 
+// Open ends: the inlet density at time level n, the vapour-branch root of
+// P_EOS(rho, T_in) = p0 (1 + p_amp sin(2 pi n / p_period)) (constant
+// p0 (1 + p_amp) when p_period <= 0).  Safeguarded Newton from rho_v inside
+// (0, rho_sp), rho_sp the vapour spinodal: a fixed number of iterations, so
+// a channel gets the same bits alone and in a batch.
+__device__ double inlet_density(const Phys& k, long long n) {
+    const double T = k.T_in_eos;
+    const double target = k.p_period > 0.0
+        ? k.p0 * (1.0 + k.p_amp * sin(2.0 * 3.14159265358979323846 * (double)n / k.p_period))
+        : k.p0 * (1.0 + k.p_amp);
+    const bool cs = (k.flags & kEosCS) != 0;
+    const double s = 1.0 + k.kappa * (1.0 - sqrt(T * k.inv_Tc));
+    const double aphi = k.a * s * s;
+    double lo = 0.0, hi = k.rho_sp, r = k.rho_v;
+    for (int it = 0; it < 60; ++it) {
+        double P, dP;
+        if (cs) {
+            const double e = 0.25 * k.b * r, o = 1.0 - e, o3 = o * o * o;
+            P = r * k.R * T * (1.0 + e * (1.0 + e * (1.0 - e))) / o3 - k.a * r * r;
+            dP = k.R * T * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (o3 * o) -
+                 2.0 * k.a * r;
+        } else {
+            const double br = k.b * r, omb = 1.0 - br, D = 1.0 + br * (2.0 - br);
+            P = r * k.R * T / omb - aphi * r * r / D;
+            dP = k.R * T / (omb * omb) - 2.0 * aphi * r * (1.0 + br) / (D * D);
+        }
+        if (P < target) lo = r; else hi = r;
+        double rn = r - (P - target) / dP;
+        if (!(rn > lo && rn < hi)) rn = 0.5 * (lo + hi);
+        r = rn;
+    }
+    return r;
+}
+
+// Zou-He on an open end (zero transverse velocity, prescribed density), in
+// deviations d_i = f_i - w_i rho_ref (the rho_ref parts cancel): with
+// J = rho u_x from the known populations, the inlet (x = 0) rebuilds d1, d5,
+// d8, the outlet (x = Nx-1, density rho_v) d3, d6, d7.  A corner node (next
+// to a plate) takes the velocity form with u = 0 (J = 0).
+template <class R>
+__device__ __forceinline__ void zou_he(R d[9], bool at_in, bool at_out, double rho_in,
+                                       const Phys& k, bool corner) {
+    const R dd = (R)0.5 * (d[2] - d[4]);
+    if (at_in) {
+        R J = (R)(rho_in - k.rho_ref) - (d[0] + d[2] + d[4] + (R)2 * (d[3] + d[6] + d[7]));
+        if (corner) J = 0;
+        d[1] = d[3] + J * ((R)2 / 3);
+        d[5] = d[7] - dd + J * ((R)1 / 6);
+        d[8] = d[6] + dd + J * ((R)1 / 6);
+    }
+    if (at_out) {
+        R J = (R)(k.rho_ref - k.rho_v) + (d[0] + d[2] + d[4] + (R)2 * (d[1] + d[5] + d[8]));
+        if (corner) J = 0;
+        d[3] = d[1] - J * ((R)2 / 3);
+        d[7] = d[5] + dd - J * ((R)1 / 6);
+        d[6] = d[8] - dd - J * ((R)1 / 6);
+    }
+}
+
 // Oscillating drive at time level n, evaluated on the device so that a channel
 // run alone and inside a batch sees the same bits.
 __device__ __forceinline__ double drive_at(const Phys& k, long long n) {
@@ -496,7 +555,7 @@ __device__ __forceinline__ int unit_of_block(int nblocks_pad) {
 // three waves per SIMD.
 template <class S, bool kMX, bool kExt>
 __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bufs<S>& B,
-                                          double drive, int unit) {
+                                          double drive, double rho_in, int unit) {
     using R = typename RealOf<S>::T;
     const int lane = threadIdx.x & (kLanes - 1);
     const int strip = unit % g.n_strips;
@@ -520,7 +579,29 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     auto on_frame = [&](const RowK& r) {
         return edge_col || (g.periodic_y && (r.sr == 0 || r.sr == g.rows - 1));
     };
-    auto held = [&](const RowK& r) { return kExt && g.frame_t && on_frame(r); };
+    // Open ends (OPEN_X): the inlet column holds T = T_in, stencils past the
+    // ends see the end column's own value (zero-gradient ghost), and the
+    // plates may carry a temperature linear in x.
+    const bool open_x = kExt && g.open_x != 0;
+    const bool at_in = open_x && cx == 0, at_out = open_x && cx == g.Nx - 1;
+    auto held = [&](const RowK& r) {
+        return (kExt && g.frame_t && on_frame(r)) || at_in;
+    };
+    auto trix = [&](auto v) {
+        if (!open_x) return tri(v);
+        auto m = at_xm(v), p = at_xp(v);
+        if (at_in) m = v;
+        if (at_out) p = v;
+        decltype(tri(v)) t;
+        t.c = v;
+        t.a = p + m;
+        t.d = p - m;
+        return t;
+    };
+    const bool ramp = kExt && k.wall_ramp != 0;
+    const R dTw_x = ramp ? (R)(k.dT_wall + (k.dT_w_end - k.dT_wall) * (double)cx / (double)(g.Nx - 1))
+                         : (R)k.dT_wall;
+    auto wall_t = [&]() { return ramp ? trix(dTw_x) : tri_const<R>(pr<R>(k).dT_wall); };
     const bool frame_rho = kExt && g.frame_rho != 0;
     const bool eos_cs = kExt && (k.flags & kEosCS) != 0;
 
@@ -654,6 +735,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             const R lo = kMX ? (R)cur.lo : (R)0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) dCur[q] = (R)cur.d[q];
+            if (open_x) zou_he<R>(dCur, at_in, at_out, rho_in, k, rA.bb_lo || rA.bb_hi);
             double drd;
             if (kMX) {
                 drd = (double)dCur[0] + (double)lo;
@@ -676,17 +758,17 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             rhoCur = (R)rho_d;
             dTA = (R)rawT;
             const double Td = k.T_ref + (double)dTA;
-            psiA = tri<double>(psi_eos<sizeof(S) == 4, kExt>(rho_d, Td, k));
+            psiA = trix(psi_eos<sizeof(S) == 4, kExt>(rho_d, Td, k));
         } else {
             drCur = 0;
             drdCur = 0.0;
             rhoCur = rho_ref;
             jxCur = jyCur = 0;
-            dTA = dTw;
+            dTA = ramp ? dTw_x : dTw;
             psiA = tri_const<double>(k.psi_wall_eff);
         }
         psi0 = psiA;
-        tn0 = tri<R>(dTA);
+        tn0 = trix(dTA);
 
         // Stages whose row lies below the rows the segment needs from them are
         // skipped (the first iterations of a segment): B needs rows from
@@ -716,8 +798,8 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             R uy = (jyPrv + (R)0.5 * Fy) * rinv;
             const bool resB = frame_rho && on_frame(rB);
             if (resB) ux = uy = 0;
-            uxB = tri<R>(ux);
-            uyB = tri<R>(uy);
+            uxB = trix(ux);
+            uyB = trix(uy);
             if (kFast || (kr - 1 >= ya && kr - 1 < yb)) {
                 // Eq. 8 theta term uses |F_m|^2 / psi^2 of the fluid-fluid force
                 R th = 0;
@@ -773,9 +855,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
                 if (held(rC)) h1 = 0;
                 acc2 = h1;
-                t1 = tri<R>(tn2.c + (R)0.5 * h1);
+                t1 = trix(tn2.c + (R)0.5 * h1);
             } else {
-                t1 = tri_const<R>(dTw);
+                t1 = wall_t();
                 acc2 = 0;
             }
             t1a = t1;
@@ -786,9 +868,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 R h2 = heat_rhs<R>(t1c, t1b, t1a, cf3, T_ref);
                 if (held(rD)) h2 = 0;
                 acc3 += (R)2 * h2;
-                t2 = tri<R>(tn3.c + (R)0.5 * h2);
+                t2 = trix(tn3.c + (R)0.5 * h2);
             } else {
-                t2 = tri_const<R>(dTw);
+                t2 = wall_t();
             }
             t2a = t2;
             // ------------- stage E: h3 on row kr-4 ------------------------
@@ -798,9 +880,9 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 R h3 = heat_rhs<R>(t2c, t2b, t2a, cf4, T_ref);
                 if (held(rE)) h3 = 0;
                 acc4 += (R)2 * h3;
-                t3 = tri<R>(tn4 + h3);
+                t3 = trix(tn4 + h3);
             } else {
-                t3 = tri_const<R>(dTw);
+                t3 = wall_t();
             }
             t3a = t3;
             // ------------- stage F: h4 and T(n+1) on row kr-5 -------------
@@ -894,7 +976,8 @@ void step_kernel(Grid g, Phys k, Bufs<S> B,
                                                                         long long n) {
     const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
     if (unit >= g.n_units) return;  // whole waves only
-    step_unit<S, kMX, kExt>(g, k, B, drive_at(k, n), unit);
+    const double rin = (kExt && g.open_x) ? inlet_density(k, n) : 0.0;
+    step_unit<S, kMX, kExt>(g, k, B, drive_at(k, n), rin, unit);
 }
 
 template <bool kExt>
@@ -904,7 +987,8 @@ void step_kernel_f64(Grid g, Phys k,
                                                                         long long n) {
     const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();
     if (unit >= g.n_units) return;
-    step_unit<double, false, kExt>(g, k, B, drive_at(k, n), unit);
+    const double rin = (kExt && g.open_x) ? inlet_density(k, n) : 0.0;
+    step_unit<double, false, kExt>(g, k, B, drive_at(k, n), rin, unit);
 }
 
 // Step i of a chunk over a batch of channels.  The slot of a unit is found by
@@ -940,7 +1024,9 @@ void step_batched_kernel(
         B.Tin = sl.off_T[t];
         B.Tout = sl.off_T[t ^ 1];
     }
-    step_unit<float, false, kExt>(g, k, B, drive_at(k, sl.n0 + step_i), unit - sl.unit_begin);
+    const double rin = (kExt && g.open_x) ? inlet_density(k, sl.n0 + step_i) : 0.0;
+    step_unit<float, false, kExt>(g, k, B, drive_at(k, sl.n0 + step_i), rin,
+                                  unit - sl.unit_begin);
 }
 
 // ---- moments: two passes over all nodes ------------------------------------
@@ -957,7 +1043,7 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
                                                      const S* __restrict__ T,
                                                      double* __restrict__ scratch,
                                                      double* __restrict__ rho_out,
-                                                     double* __restrict__ T_out) {
+                                                     double* __restrict__ T_out, long long n_t) {
     const int n = g.Nx * g.Ny;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -970,7 +1056,9 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
         psi[i] = k.psi_wall_eff;
         jx[i] = jy[i] = 0.0;
         rho_out[i] = 0.0;
-        T_out[i] = k.T_ref + k.dT_wall;
+        T_out[i] = k.T_ref + (k.wall_ramp ? k.dT_wall + (k.dT_w_end - k.dT_wall) * (double)cx /
+                                                              (double)(g.Nx - 1)
+                                          : k.dT_wall);
         return;
     }
     const unsigned x = (unsigned)cx;
@@ -978,6 +1066,16 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
     const unsigned xp = (unsigned)(cx == g.Nx - 1 ? 0 : cx + 1);
     S d[9];
     pull_row<S>(f, g, r, x, xm, xp, d);
+    if (g.open_x && (cx == 0 || cx == g.Nx - 1)) {
+        using R = typename RealOf<S>::T;
+        R dr_[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dr_[q] = (R)d[q];
+        zou_he<R>(dr_, cx == 0, cx == g.Nx - 1, cx == 0 ? inlet_density(k, n_t) : 0.0, k,
+                  r.bb_lo || r.bb_hi);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) d[q] = (S)dr_[q];
+    }
     double dr = 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) dr += (double)d[q];
@@ -1013,8 +1111,9 @@ __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
     const double* psi = scratch;
     const double* jx = scratch + n;
     const double* jy = scratch + 2 * n;
-    const int xm = cx == 0 ? g.Nx - 1 : cx - 1;
-    const int xp = cx == g.Nx - 1 ? 0 : cx + 1;
+    // periodic in x, or the end column itself past an open end
+    const int xm = cx == 0 ? (g.open_x ? 0 : g.Nx - 1) : cx - 1;
+    const int xp = cx == g.Nx - 1 ? (g.open_x ? cx : 0) : cx + 1;
     int ys = y - 1, yn = y + 1;
     if (g.periodic_y) {
         if (ys < 0) ys += g.Ny;
@@ -1080,10 +1179,10 @@ __global__ __launch_bounds__(256) void init_kernel(Grid g, Phys k, const double*
             f[q * g.plane + o] = (S)v;
         }
     }
-    // T = T_0 = T_ref, or T_w on a held frame node
+    // T = T_0 = T_ref, T_w on a held frame node, T_in on an open inlet
     const bool held = g.frame_t && (cx == 0 || cx == g.Nx - 1 ||
                                     (g.periodic_y && (y == 0 || y == g.Ny - 1)));
-    T[o] = held ? (S)k.dT_wall : (S)0;
+    T[o] = (g.open_x && cx == 0) ? (S)k.dT_in : (held ? (S)k.dT_wall : (S)0);
 }
 
 // ---- deterministic FP64 reduction ------------------------------------------
@@ -1160,7 +1259,7 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
 }
 
 bool needs_ext(const Grid& g, const Phys& k) {
-    return g.frame_t || g.frame_rho || (k.flags & kEosCS);
+    return g.frame_t || g.frame_rho || g.open_x || k.wall_ramp || (k.flags & kEosCS);
 }
 
 template <class S, bool kMX>
@@ -1213,7 +1312,7 @@ static hipError_t moments_impl(const Grid& g, const Phys& k, const S* f, const f
                                double* Tout, int64_t n_t, hipStream_t s) {
     const int n = g.Nx * g.Ny;
     hipLaunchKernelGGL((moments_pass1<S, kMX>), dim3(blocks_for(n, 256)), dim3(256), 0, s, g, k,
-                       f, f0lo, T, scratch, rho, Tout);
+                       f, f0lo, T, scratch, rho, Tout, (long long)n_t);
     hipLaunchKernelGGL(moments_pass2, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, k,
                        (const double*)scratch, (const double*)rho, ux, uy, (long long)n_t);
     return hipGetLastError();

@@ -143,6 +143,43 @@ Eos eos_of(const lbm_params& p, double Tc) {
     return E;
 }
 
+// Open ends (LBM_OPEN_X): the boundary EOS pressures are taken at the inlet
+// temperature; p0 = P_EOS(rho_v, T_in).  The inlet density is a root on the
+// vapour branch, below the vapour spinodal (first zero of dP/drho; the
+// packing limit when the isotherm has none).
+double inlet_temperature(const lbm_params& p) { return p.T_in > 0.0 ? p.T_in : p.T_0; }
+double inlet_p0(const lbm_params& p) {
+    double Tc = p.T_c, rc;
+    if (!(Tc > 0.0)) critical_of(p, &rc, &Tc);
+    return eos_of(p, Tc).P(p.rho_v, inlet_temperature(p));
+}
+bool inlet_bracket(const lbm_params& p, double* rho_sp, double* p_max, void*) {
+    double Tc = p.T_c, rc;
+    if (!(Tc > 0.0)) critical_of(p, &rc, &Tc);
+    const Eos E = eos_of(p, Tc);
+    const double T = inlet_temperature(p), rmax = E.rmax();
+    if (!(T > 0.0)) return false;
+    double hi = rmax * (1.0 - 1e-9);
+    const int n = 8192;
+    double prev = rmax * 1e-9;
+    for (int i = 1; i < n; ++i) {
+        const double r = rmax * i / n;
+        if (E.dPdr(r, T) <= 0.0) {
+            double lo = prev, h = r;
+            for (int it = 0; it < 100; ++it) {
+                const double mid = 0.5 * (lo + h);
+                if (E.dPdr(mid, T) > 0.0) lo = mid; else h = mid;
+            }
+            hi = lo;
+            break;
+        }
+        prev = r;
+    }
+    if (rho_sp) *rho_sp = hi;
+    if (p_max) *p_max = E.P(hi, T);
+    return true;
+}
+
 template <class F>
 double bisect(F f, double lo, double hi) {
     const double flo = f(lo);
@@ -231,7 +268,16 @@ lbm_status validate(const lbm_params& p) {
     if (p.Ny < (per ? 3 : 4)) return fail(LBM_EINVAL, "Ny = %d too small", p.Ny);
     if (p.precision < LBM_FP32_DEV || p.precision > LBM_FP32_DEV_MASSEXACT)
         return fail(LBM_EINVAL, "unknown precision %d", p.precision);
-    if (p.flags & ~63u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & ~127u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & LBM_OPEN_X) {
+        if (p.Nx < 4) return fail(LBM_EINVAL, "LBM_OPEN_X needs Nx >= 4");
+        double pmax;
+        if (!inlet_bracket(p, nullptr, &pmax, nullptr))
+            return fail(LBM_EINVAL, "LBM_OPEN_X: no vapour state at the inlet temperature");
+        const double p0 = inlet_p0(p);
+        if (!(p0 * (1.0 + std::fabs(p.p_amp)) < pmax) || !(p0 * (1.0 - std::fabs(p.p_amp)) > 0.0))
+            return fail(LBM_EINVAL, "LBM_OPEN_X: inlet pressure range leaves the vapour branch");
+    }
     if ((p.flags & LBM_FRAME_RHO) && !(p.rho_frame > 0.0))
         return fail(LBM_EINVAL, "LBM_FRAME_RHO needs rho_frame > 0");
     if (p.G == 0.0) return fail(LBM_EINVAL, "G must be nonzero");
@@ -310,6 +356,7 @@ void fill_grid(const lbm_params& p, const Layout& L, int seg_rows, Grid& g) {
     g.periodic_y = (p.flags & LBM_PERIODIC_Y) ? 1 : 0;
     g.frame_t = (p.flags & LBM_FRAME_T) ? 1 : 0;
     g.frame_rho = (p.flags & LBM_FRAME_RHO) ? 1 : 0;
+    g.open_x = (p.flags & LBM_OPEN_X) ? 1 : 0;
     g.y_first = g.periodic_y ? 0 : 1;
     g.plane = (unsigned)L.plane;
     g.n_strips = (p.Nx + lbmk::kOwned - 1) / lbmk::kOwned;
@@ -354,6 +401,16 @@ void fill_phys(const lbm_params& p, Phys& k) {
     k.g_y = p.g_y;
     k.rho_v = p.rho_v;
     k.rho_frame = p.rho_frame;
+    if (p.flags & LBM_OPEN_X) {
+        k.T_in_eos = p.T_in > 0.0 ? p.T_in : p.T_0;
+        k.p0 = inlet_p0(p);
+        inlet_bracket(p, &k.rho_sp, nullptr, nullptr);
+        k.p_amp = p.p_amp;
+        k.p_period = p.p_period;
+    }
+    k.dT_in = (p.T_in > 0.0 ? p.T_in : p.T_0) - p.T_0;
+    k.wall_ramp = p.T_w_end > 0.0 ? 1 : 0;
+    k.dT_w_end = (p.T_w_end > 0.0 ? p.T_w_end : p.T_w) - p.T_0;
     k.rkA = p.R;
     k.rkB1 = p.a * kap * (1.0 + kap) / std::sqrt(p.T_c);
     k.rkB2 = p.a * kap * kap / p.T_c;

@@ -13,7 +13,8 @@ _MAP = dict(Nx="Nx", Ny="Ny", a="a", b="b", R="R", omega="omega", T_c="Tc", G="G
             s_zeta="s_zeta", s_j="s_j", s_q="s_q", tau_g="tau_g", tau_l="tau_l",
             rho_g="rho_g", rho_l="rho_l", C_v="Cv", lambda_="lam", T_0="T0", T_w="Tw",
             g_osc="g_osc", period="period", g_x="gx", g_y="gy", rho_v="rho_v",
-            rho_frame="rho_frame", flags="flags")
+            rho_frame="rho_frame", p_amp="p_amp", p_period="p_period", T_w_end="Tw_end",
+            T_in="T_in", flags="flags")
 
 
 def to_oracle(orc, p):

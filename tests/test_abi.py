@@ -62,7 +62,7 @@ def test_library_coexistence_matches_oracle(L, orc, frac):
 
 @pytest.mark.parametrize("bad", [dict(Nx=2), dict(Ny=3), dict(s_e=0.9), dict(s_q=2.0),
                                  dict(tau_g=0.5), dict(G=0.0), dict(precision=7),
-                                 dict(flags=64), dict(flags=128)])
+                                 dict(flags=128), dict(flags=256)])
 def test_workspace_bytes_rejects_invalid(L, bad):
     p = lbm.lbm_params_default(**bad)
     assert lbm.lbm_workspace_bytes(p) == 0

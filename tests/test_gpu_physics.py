@@ -208,3 +208,19 @@ def test_cs_eos_parity(orc, precision, flags):
     print(e, flush=True)
     tol = (1e-11, 1e-9, 1e-11) if precision == lbm.LBM_FP64 else (1e-5, 1e-5, 1e-5)
     assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
+
+
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+@pytest.mark.parametrize("Nx,Ny", [(60, 20), (131, 24)])
+def test_open_channel_parity(orc, precision, Nx, Ny):
+    """Sec. 3.3 boundary set (OPEN_X): Zou-He oscillating-pressure inlet and
+    constant-pressure outlet, plates at 0.86 -> 0.56 T_c along x, gravity
+    +x, hydrophobic plates; 200 steps against the oracle (the end columns and
+    the strips that touch them included)."""
+    _case("open channel %dx%d precision=%d, 200 steps" % (Nx, Ny, precision))
+    p = configs.open_channel(Nx, Ny, p_period=300.0, precision=precision)
+    rho0 = configs.initial_density(p, seed=21)
+    e = field_errors(_gpu(p, rho0, 200), _oracle(orc, p, rho0, 200), fluid_mask(Nx, Ny))
+    print(e, flush=True)
+    tol = (1e-11, 1e-9, 1e-11) if precision == lbm.LBM_FP64 else (1e-5, 1e-5, 1e-5)
+    assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
