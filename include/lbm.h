@@ -77,7 +77,7 @@ enum {
                               P = rho R T (1 + e + e^2 - e^3) / (1 - e)^3
                               - a rho^2, e = b rho / 4 (usual constants
                               a = 1, b = 4, R = 1); omega is then unused   */
-    LBM_OPEN_X = 64u       /* Sec. 3.3 boundary set: x is not periodic;
+    LBM_OPEN_X = 64u,      /* Sec. 3.3 boundary set: x is not periodic;
                               column 0 is a Zou-He pressure inlet, column
                               Nx-1 a Zou-He pressure outlet (zero transverse
                               velocity).  Pressures are EOS pressures:
@@ -87,6 +87,12 @@ enum {
                               are their vapour-branch roots.  Stencils past
                               the ends see the boundary column's own values;
                               the inlet column holds T = T_in.              */
+    LBM_PHASE_PROPS = 128u /* lambda and C_v interpolated between the gas
+                              values (lambda, C_v) and the liquid values
+                              (lambda_l, C_v_l) with the clamped fraction of
+                              Eq. 5; the conduction term of Eq. 16 becomes
+                              [lambda lap T + grad(lambda).grad(T)] / (rho C_v),
+                              solid nodes carrying the gas values           */
 };
 
 /* Parameters, named as in the paper.  lbm_params_default() fills the paper's
@@ -114,10 +120,12 @@ typedef struct {
     double T_w_end;         /* > 0: plate temperature linear in x, from T_w at
                                x = 0 to T_w_end at x = Nx-1 (Sec. 3.3)          */
     double T_in;            /* LBM_OPEN_X inlet temperature; <= 0: T_0          */
+    double lambda_l, C_v_l; /* LBM_PHASE_PROPS liquid conductivity and heat
+                               capacity (lambda, C_v are then the gas values)    */
     int32_t precision;      /* LBM_FP32_DEV, LBM_FP64 or LBM_FP32_DEV_MASSEXACT   */
     uint32_t flags;         /* LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y |
                                LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS |
-                               LBM_OPEN_X                                        */
+                               LBM_OPEN_X | LBM_PHASE_PROPS                      */
 } lbm_params;
 
 /* Fill *p with the defaults: Nx = 128, Ny = 32, a = 3/49, b = 2/21, R = 1,

@@ -62,6 +62,13 @@
  *    ghost (the boundary column's own psi, T, u).  The inlet column holds
  *    T = T_in; the outlet's T evolves.  With Tw_end > 0 the plates'
  *    temperature varies linearly from Tw at x = 0 to Tw_end at x = Nx-1.
+ *  - Phase-dependent conductivity and heat capacity (flag PHASE_PROPS; the
+ *    paper keeps them equal in both phases): lambda(rho) and C_v(rho) are
+ *    interpolated between the gas and liquid values with the clamped
+ *    fraction of Eq. 5, and the conduction term of Eq. 16 becomes
+ *    [lambda lap T + grad(lambda) . grad(T)] / (rho C_v), grad(lambda) by
+ *    the same nine-point stencil on lambda(rho(n)); solid nodes carry the
+ *    gas values.
  */
 #define _USE_MATH_DEFINES
 #include <math.h>
@@ -79,6 +86,7 @@
                             /* density rho_frame                            */
 #define ORC_EOS_CS 32u      /* Carnahan-Starling EOS in place of Eq. 11     */
 #define ORC_OPEN_X 64u      /* Zou-He pressure inlet / outlet in x          */
+#define ORC_PHASE_PROPS 128u /* lambda and C_v interpolated between phases   */
 
 typedef struct {
     int32_t Nx, Ny;
@@ -94,6 +102,7 @@ typedef struct {
     double rho_frame;             /* FRAME_RHO reservoir density */
     double p_amp, p_period;       /* OPEN_X inlet pressure oscillation */
     double Tw_end, T_in;          /* plate T at x = Nx-1 (<= 0: uniform); inlet T (<= 0: T0) */
+    double lam_l, Cv_l;           /* PHASE_PROPS liquid values (lambda, Cv are the gas's) */
     uint32_t flags;
     int32_t pad_;
 } orc_params;
@@ -631,6 +640,21 @@ static void macroscopic(orc_sim* s) {
         }
 }
 
+/* phase fraction of Eq. 5 (clamped); 0 on solid nodes */
+static double phase_frac(const orc_params* p, double rho) {
+    double f = (rho - p->rho_g) / (p->rho_l - p->rho_g);
+    return f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+}
+static double lam_at(const orc_params* p, const orc_sim* s, int x, int y) {
+    if (!(p->flags & ORC_PHASE_PROPS)) return p->lambda;
+    if (is_solid(p, y)) return p->lambda;
+    return p->lambda + (p->lam_l - p->lambda) * phase_frac(p, s->rho[IDX(p, x, y)]);
+}
+static double cv_at(const orc_params* p, double rho) {
+    if (!(p->flags & ORC_PHASE_PROPS)) return p->Cv;
+    return p->Cv + (p->Cv_l - p->Cv) * phase_frac(p, rho);
+}
+
 /* K(T) of Eq. 16 at every fluid node for the stage field Ts (T_w on solid
  * rows), with rho and u frozen at time level n. */
 static void heat_rhs(const orc_sim* s, const double* Ts, double* out) {
@@ -639,21 +663,26 @@ static void heat_rhs(const orc_sim* s, const double* Ts, double* out) {
         for (int x = 0; x < p->Nx; ++x) {
             size_t c = IDX(p, x, y);
             if (is_solid(p, y)) { out[c] = 0.0; continue; }
-            double tx = 0.0, ty = 0.0, lap = 0.0, div = 0.0;
+            double tx = 0.0, ty = 0.0, lap = 0.0, div = 0.0, lx = 0.0, ly = 0.0;
             for (int i = 1; i < 9; ++i) {
                 int xn = nbx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
                 size_t cn = IDX(p, xn, yn);
                 double w = wgt(i);
                 tx += w * EX[i] * Ts[cn];
                 ty += w * EY[i] * Ts[cn];
+                double ln = lam_at(p, s, xn, yn);
+                lx += w * EX[i] * ln;
+                ly += w * EY[i] * ln;
                 lap += 2.0 * w * (Ts[cn] - Ts[c]);
                 double uxn = is_solid(p, yn) ? 0.0 : s->ux[cn];
                 double uyn = is_solid(p, yn) ? 0.0 : s->uy[cn];
                 div += w * (EX[i] * uxn + EY[i] * uyn);
             }
-            double r = s->rho[c], T = Ts[c];
-            out[c] = -(s->ux[c] * tx + s->uy[c] * ty) + p->lambda / (r * p->Cv) * lap -
-                     T / (r * p->Cv) * orc_dpdT(p, r, T) * div;
+            double r = s->rho[c], T = Ts[c], cv = cv_at(p, r);
+            double cond = (p->flags & ORC_PHASE_PROPS) ? lam_at(p, s, x, y) * lap + lx * tx + ly * ty
+                                                       : p->lambda * lap;
+            out[c] = -(s->ux[c] * tx + s->uy[c] * ty) + cond / (r * cv) -
+                     T / (r * cv) * orc_dpdT(p, r, T) * div;
         }
 }
 

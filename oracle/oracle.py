@@ -27,6 +27,7 @@ FRAME_T = 8
 FRAME_RHO = 16
 EOS_CS = 32
 OPEN_X = 64
+PHASE_PROPS = 128
 
 
 def build(force: bool = False) -> str:
@@ -57,6 +58,7 @@ class OrcParams(C.Structure):
         ("rho_frame", C.c_double),
         ("p_amp", C.c_double), ("p_period", C.c_double),
         ("Tw_end", C.c_double), ("T_in", C.c_double),
+        ("lam_l", C.c_double), ("Cv_l", C.c_double),
         ("flags", C.c_uint32), ("pad_", C.c_int32),
     ]
 

@@ -28,7 +28,7 @@
 namespace lbmk {
 namespace {
 
-constexpr uint32_t kFreezeT = 1u, kSinglePhase = 2u, kEosCS = 32u;
+constexpr uint32_t kFreezeT = 1u, kSinglePhase = 2u, kEosCS = 32u, kPhaseProps = 128u;
 
 // ---- lane shifts (DPP wave_shr:1 / wave_shl:1) ---------------------------
 // at_xm(v): the value lane l-1 holds (column x-1); at_xp: lane l+1 (x+1).  The
@@ -403,9 +403,15 @@ template <class R>
 struct Coef {
     R ux, uy, q1, q2, q3;
 };
+// lam_c, glx, gly, inv_cv: the conductivity at the node, its gradient and
+// 1/C_v (constants unless lambda and C_v depend on the phase).  The
+// conduction term [lambda lap T + grad(lambda).grad(T)] / (rho C_v) is
+// carried as q3 lap T plus a shift of the advecting velocity by
+// -grad(lambda) / (rho C_v).
 template <class R>
 __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, R T_ref,
-                                             const PhysR<R>& pc, bool cs) {
+                                             const PhysR<R>& pc, bool cs, bool props,
+                                             R lam_c, R glx, R gly, R inv_cv) {
     R A, r2D, c;
     if (cs) {
         // Carnahan-Starling: T (dP/dT)_rho = rho R Z(e) T, no sqrt(T) term
@@ -414,7 +420,7 @@ __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, R 
         const R inv = rcp_r(o3 * rho);
         A = rho * rho * pc.rkA * ((R)1 + e * ((R)1 + e * ((R)1 - e))) * inv;
         r2D = 0;
-        c = pc.inv_Cv * o3 * inv;
+        c = (props ? inv_cv : pc.inv_Cv) * o3 * inv;
     } else {
         const R br = pc.b * rho;
         const R omb = (R)1 - br;
@@ -422,14 +428,14 @@ __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, R 
         const R inv = rcp_r(omb * D * rho);  // 1 / ((1 - b rho) D rho)
         A = rho * rho * pc.rkA * D * inv;
         r2D = rho * rho * rho * omb * inv;
-        c = pc.inv_Cv * omb * D * inv;
+        c = (props ? inv_cv : pc.inv_Cv) * omb * D * inv;
     }
     Coef<R> q;
-    q.ux = ux;
-    q.uy = uy;
+    q.ux = props ? ux - c * glx : ux;
+    q.uy = props ? uy - c * gly : uy;
     q.q1 = c * divu * (A - pc.rkB2 * r2D);
     q.q2 = c * divu * pc.rkB1 * r2D;
-    q.q3 = c * pc.lambda;
+    q.q3 = c * (props ? lam_c : pc.lambda);
     if (sizeof(R) == 4) {
         const R rs = (R)__builtin_amdgcn_rsqf((float)Tn);  // 1 / sqrt(T_n)
         const R sn = Tn * rs;
@@ -603,6 +609,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                          : (R)k.dT_wall;
     auto wall_t = [&]() { return ramp ? trix(dTw_x) : tri_const<R>(pr<R>(k).dT_wall); };
     const bool frame_rho = kExt && g.frame_rho != 0;
+    const bool props = kExt && (k.flags & kPhaseProps) != 0;
     const bool eos_cs = kExt && (k.flags & kEosCS) != 0;
 
     const int ya = g.y_first + seg * g.seg_rows;
@@ -648,6 +655,8 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     Tri<R> ux1, ux2, ux3, uy1, uy2, uy3;
     // heat coefficients rows k-2 .. k-5
     Coef<R> cf2, cf3, cf4, cf5;
+    // phase-dependent conductivity (optional): rows k-1, k-2, k-3
+    Tri<R> lam1, lam2, lam3;
     // RK stage fields: T1 rows k-2..k-4, T2 rows k-3..k-5, T3 rows k-4..k-6
     Tri<R> t1a, t1b, t1c, t2a, t2b, t2c, t3a, t3b, t3c;
     R acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0;  // sum of the h's, rows k-2 .. k-5
@@ -659,6 +668,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     tn0 = tn1 = tn2 = tn3 = tri_const<R>(dTw);
     ux1 = ux2 = ux3 = uy1 = uy2 = uy3 = tri_const<R>(0);
     cf2 = cf3 = cf4 = cf5 = Coef<R>{0, 0, 0, 0, 0};
+    lam1 = lam2 = lam3 = tri_const<R>((R)k.lambda);
     t1a = t1b = t1c = t2a = t2b = t2c = t3a = t3b = t3c = tri_const<R>(dTw);
 
     // One buffer resource covers every buffer of the step (they share one
@@ -800,6 +810,11 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             if (resB) ux = uy = 0;
             uxB = trix(ux);
             uyB = trix(uy);
+            if (props) {  // lambda(rho(n)) of row kr-1, gas..liquid by the Eq. 5 fraction
+                R fr = (rho - kr_.rho_g) * kr_.inv_drho;
+                fr = fr < (R)0 ? (R)0 : (fr > (R)1 ? (R)1 : fr);
+                lam1 = trix((R)k.lambda + (R)(k.lam_l - k.lambda) * fr);
+            }
             if (kFast || (kr - 1 >= ya && kr - 1 < yb)) {
                 // Eq. 8 theta term uses |F_m|^2 / psi^2 of the fluid-fluid force
                 R th = 0;
@@ -841,6 +856,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         } else {
             uxB = tri_const<R>(0);
             uyB = tri_const<R>(0);
+            if (props) lam1 = tri_const<R>((R)k.lambda);  // solid nodes: gas values
         }
         ux1 = uxB;
         uy1 = uyB;
@@ -851,7 +867,18 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             Tri<R> t1;
             if (kFast || (rC.fluid && needC)) {
                 const R dv = div_u<R>(ux3, ux2, ux1, uy3, uy2, uy1);
-                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, cv, eos_cs);
+                R lam_c = cv.lambda, glx = 0, gly = 0, inv_cv = cv.inv_Cv;
+                if (props) {
+                    const R third = (R)1 / 3, twelfth = (R)1 / 12;
+                    lam_c = lam2.c;
+                    glx = lam2.d * third + (lam1.d + lam3.d) * twelfth;
+                    gly = (lam1.c - lam3.c) * third + (lam1.a - lam3.a) * twelfth;
+                    R fr = (rhoP2 - kr_.rho_g) * kr_.inv_drho;
+                    fr = fr < (R)0 ? (R)0 : (fr > (R)1 ? (R)1 : fr);
+                    inv_cv = rcp_r((R)(1.0 / k.inv_Cv) + (R)(k.cv_l - 1.0 / k.inv_Cv) * fr);
+                }
+                cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, cv, eos_cs,
+                                   props, lam_c, glx, gly, inv_cv);
                 R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
                 if (held(rC)) h1 = 0;
                 acc2 = h1;
@@ -910,6 +937,10 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         tn2 = tn1;
         tn1 = tn0;
         psi2 = psi1;
+        if (props) {
+            lam3 = lam2;
+            lam2 = lam1;
+        }
         psi1 = psi0;
         ux3 = ux2;
         ux2 = ux1;
@@ -1259,7 +1290,8 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
 }
 
 bool needs_ext(const Grid& g, const Phys& k) {
-    return g.frame_t || g.frame_rho || g.open_x || k.wall_ramp || (k.flags & kEosCS);
+    return g.frame_t || g.frame_rho || g.open_x || k.wall_ramp ||
+           (k.flags & (kEosCS | kPhaseProps));
 }
 
 template <class S, bool kMX>

@@ -282,7 +282,8 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
     bool ext = false;  // some slot needs the build with the optional features
     for (size_t j = 0; j < act.size(); ++j) {
         SlotState& s = P->slots[act[j]];
-        ext = ext || (s.p.flags & (LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS | LBM_OPEN_X)) ||
+        ext = ext || (s.p.flags & (LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS | LBM_OPEN_X |
+                                   LBM_PHASE_PROPS)) ||
               s.p.T_w_end > 0.0;
         if (!s.ready_waited) {
             PCHK(hipStreamWaitEvent(P->main, s.ready, 0));

@@ -268,7 +268,9 @@ lbm_status validate(const lbm_params& p) {
     if (p.Ny < (per ? 3 : 4)) return fail(LBM_EINVAL, "Ny = %d too small", p.Ny);
     if (p.precision < LBM_FP32_DEV || p.precision > LBM_FP32_DEV_MASSEXACT)
         return fail(LBM_EINVAL, "unknown precision %d", p.precision);
-    if (p.flags & ~127u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & ~255u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if ((p.flags & LBM_PHASE_PROPS) && !(p.lambda_l >= 0.0 && p.C_v_l > 0.0))
+        return fail(LBM_EINVAL, "LBM_PHASE_PROPS needs lambda_l >= 0 and C_v_l > 0");
     if (p.flags & LBM_OPEN_X) {
         if (p.Nx < 4) return fail(LBM_EINVAL, "LBM_OPEN_X needs Nx >= 4");
         double pmax;
@@ -410,6 +412,8 @@ void fill_phys(const lbm_params& p, Phys& k) {
     }
     k.dT_in = (p.T_in > 0.0 ? p.T_in : p.T_0) - p.T_0;
     k.wall_ramp = p.T_w_end > 0.0 ? 1 : 0;
+    k.lam_l = p.lambda_l;
+    k.cv_l = p.C_v_l;
     k.dT_w_end = (p.T_w_end > 0.0 ? p.T_w_end : p.T_w) - p.T_0;
     k.rkA = p.R;
     k.rkB1 = p.a * kap * (1.0 + kap) / std::sqrt(p.T_c);

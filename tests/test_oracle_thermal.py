@@ -217,3 +217,42 @@ def test_reservoir_frame_values_held(orc):
     assert np.all(rho[frame] == 0.29) and np.all(ux[frame] == 0) and np.all(uy[frame] == 0)
     assert np.all(T[frame] == p.Tw)
     assert abs(rho[~frame].sum() - rho0[~frame].sum()) > 1e-6 * rho0.sum()
+
+
+def test_phase_props_reduce_to_constant_properties(orc):
+    """PHASE_PROPS with equal gas and liquid values is the constant-property
+    energy equation."""
+    Nx, Ny = 11, 9
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y, lam=0.2, Cv=3.0)
+    x, y = _grid(Nx, Ny)
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(0.3, 6.5, (Ny, Nx))
+    ux, uy = rng.uniform(-0.05, 0.05, (2, Ny, Nx))
+    T = p.T0 * (1 + 0.01 * rng.uniform(-1, 1, (Ny, Nx)))
+    K0 = orc.heat_rhs(p, rho, ux, uy, T)
+    p.flags |= orc.PHASE_PROPS
+    p.lam_l, p.Cv_l = p.lam, p.Cv
+    np.testing.assert_allclose(orc.heat_rhs(p, rho, ux, uy, T), K0, rtol=1e-13, atol=1e-18)
+
+
+def test_phase_props_conduction_exact_on_polynomials(orc):
+    """rho linear in x inside (rho_g, rho_l) makes lambda(rho) linear,
+    T = T0 + b x^2: the nine-point form lambda lap T + grad(lambda) . grad(T)
+    equals d/dx[(l0 + a x) 2 b x] = 2 b lambda(x) + 2 a b x exactly; divided
+    by rho C_v(rho) with C_v interpolated the same way."""
+    Nx, Ny = 15, 7
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y | orc.PHASE_PROPS,
+                           lam=0.1, Cv=4.0)
+    p.lam_l, p.Cv_l = 0.6, 2.5
+    x, y = _grid(Nx, Ny)
+    frac = 0.1 + 0.05 * x
+    rho = p.rho_g + frac * (p.rho_l - p.rho_g)
+    bT = 1e-5
+    T = p.T0 + bT * x * x
+    K = orc.heat_rhs(p, rho, np.zeros_like(rho), np.zeros_like(rho), T)
+    lam = p.lam + (p.lam_l - p.lam) * frac
+    a = (p.lam_l - p.lam) * 0.05
+    cv = p.Cv + (p.Cv_l - p.Cv) * frac
+    expect = (2 * bT * lam + a * 2 * bT * x) / (rho * cv)
+    inner = (slice(None), slice(1, -1))
+    np.testing.assert_allclose(K[inner], expect[inner], rtol=1e-10)
