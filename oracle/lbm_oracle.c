@@ -69,6 +69,12 @@
  *    [lambda lap T + grad(lambda) . grad(T)] / (rho C_v), grad(lambda) by
  *    the same nine-point stencil on lambda(rho(n)); solid nodes carry the
  *    gas values.
+ *  - Sec. 3.2 plates (flag TOP_MIXED; Fig. 4 is not available): the top
+ *    plate holds T_w on the columns cold_x0 <= x < cold_x1 (the cold centre)
+ *    and is adiabatic elsewhere; the bottom plate holds Tw_bot.  Adiabatic
+ *    means zero normal gradient at the half-way wall: wherever a stencil
+ *    reaches an adiabatic top node it reads the fluid node just below it,
+ *    at the same RK stage.
  */
 #define _USE_MATH_DEFINES
 #include <math.h>
@@ -87,6 +93,8 @@
 #define ORC_EOS_CS 32u      /* Carnahan-Starling EOS in place of Eq. 11     */
 #define ORC_OPEN_X 64u      /* Zou-He pressure inlet / outlet in x          */
 #define ORC_PHASE_PROPS 128u /* lambda and C_v interpolated between phases   */
+#define ORC_TOP_MIXED 256u  /* Sec. 3.2: cold centre and adiabatic sides on  */
+                            /* the top plate, bottom plate at Tw_bot        */
 
 typedef struct {
     int32_t Nx, Ny;
@@ -103,6 +111,8 @@ typedef struct {
     double p_amp, p_period;       /* OPEN_X inlet pressure oscillation */
     double Tw_end, T_in;          /* plate T at x = Nx-1 (<= 0: uniform); inlet T (<= 0: T0) */
     double lam_l, Cv_l;           /* PHASE_PROPS liquid values (lambda, Cv are the gas's) */
+    double Tw_bot;                /* TOP_MIXED bottom plate T (<= 0: T0) */
+    int32_t cold_x0, cold_x1;     /* TOP_MIXED cold columns of the top plate */
     uint32_t flags;
     int32_t pad_;
 } orc_params;
@@ -462,6 +472,21 @@ static int wrapy(const orc_params* p, int y) {
 #define IDX(p, x, y) ((size_t)(y) * (size_t)(p)->Nx + (size_t)(x))
 #define FIDX(p, i, x, y) (((size_t)(i) * (size_t)(p)->Ny + (size_t)(y)) * (size_t)(p)->Nx + (size_t)(x))
 
+/* held temperature of a solid node (TOP_MIXED: the bottom plate's value on
+ * row 0; the top plate's stored value is T_w, read only on its cold columns) */
+static double t_plate(const orc_params* p, int x, int y) {
+    if ((p->flags & ORC_TOP_MIXED) && !(p->flags & ORC_PERIODIC_Y) && y == 0) return p->Tw_bot > 0.0 ? p->Tw_bot : p->T0;
+    return tw_at(p, x);
+}
+/* the node a temperature stencil reads for (x, y): an adiabatic top node
+ * (TOP_MIXED, outside the cold columns) mirrors the fluid node below it */
+static size_t t_src(const orc_params* p, int x, int y) {
+    if ((p->flags & ORC_TOP_MIXED) && !(p->flags & ORC_PERIODIC_Y) && y == p->Ny - 1 &&
+        !(x >= p->cold_x0 && x < p->cold_x1))
+        return IDX(p, x, y - 1);
+    return IDX(p, x, y);
+}
+
 orc_sim* orc_sim_new(const orc_params* p) {
     if (p->Nx < 1 || p->Ny < 1) return NULL;
     if (!(p->flags & ORC_PERIODIC_Y) && p->Ny < 3) return NULL;
@@ -504,7 +529,7 @@ void orc_sim_init(orc_sim* s, const double* rho0, double rho_uniform) {
                 feq[i] = v;
             }
             for (int i = 0; i < 9; ++i) s->f[FIDX(p, i, x, y)] = is_solid(p, y) ? 0.0 : feq[i];
-            double Tb = is_solid(p, y) ? tw_at(p, x) : p->Tw;
+            double Tb = is_solid(p, y) ? t_plate(p, x, y) : p->Tw;
             if ((p->flags & ORC_OPEN_X) && x == 0 && !is_solid(p, y)) Tb = t_inlet(p);
             s->T[IDX(p, x, y)] = t_held(p, x, y) ? Tb : p->T0;
         }
@@ -668,12 +693,13 @@ static void heat_rhs(const orc_sim* s, const double* Ts, double* out) {
                 int xn = nbx(p, x + EX[i]), yn = wrapy(p, y + EY[i]);
                 size_t cn = IDX(p, xn, yn);
                 double w = wgt(i);
-                tx += w * EX[i] * Ts[cn];
-                ty += w * EY[i] * Ts[cn];
+                double Tn = Ts[t_src(p, xn, yn)];
+                tx += w * EX[i] * Tn;
+                ty += w * EY[i] * Tn;
                 double ln = lam_at(p, s, xn, yn);
                 lx += w * EX[i] * ln;
                 ly += w * EY[i] * ln;
-                lap += 2.0 * w * (Ts[cn] - Ts[c]);
+                lap += 2.0 * w * (Tn - Ts[c]);
                 double uxn = is_solid(p, yn) ? 0.0 : s->ux[cn];
                 double uyn = is_solid(p, yn) ? 0.0 : s->uy[cn];
                 div += w * (EX[i] * uxn + EY[i] * uyn);

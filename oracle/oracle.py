@@ -28,6 +28,7 @@ FRAME_RHO = 16
 EOS_CS = 32
 OPEN_X = 64
 PHASE_PROPS = 128
+TOP_MIXED = 256
 
 
 def build(force: bool = False) -> str:
@@ -59,6 +60,7 @@ class OrcParams(C.Structure):
         ("p_amp", C.c_double), ("p_period", C.c_double),
         ("Tw_end", C.c_double), ("T_in", C.c_double),
         ("lam_l", C.c_double), ("Cv_l", C.c_double),
+        ("Tw_bot", C.c_double), ("cold_x0", C.c_int32), ("cold_x1", C.c_int32),
         ("flags", C.c_uint32), ("pad_", C.c_int32),
     ]
 
