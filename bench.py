@@ -287,6 +287,40 @@ def open_channel_run(steps=6000, every=2000):
     return out
 
 
+def gravity_plate_run(steps=40000, every=2500):
+    """Sec. 3.2 condensation under gravity on the paper's 100 x 300 box (cold
+    middle third of the top plate at 0.65 T_c, adiabatic sides, bottom plate
+    at T_sat, gravity 1e-4 toward it, 137.82 degree plates), FP32: throughput
+    and, every `every` steps, the liquid and its largest connected set (node
+    count, centroid height, contact with either plate); the step at which
+    that set leaves the top half, and the one at which it reaches the bottom
+    tenth."""
+    from paper_1803_01756_amd import analysis, configs, lbm
+    p = configs.gravity_plate()
+    s = lbm.Sim(p, configs.initial_density(p, seed=32))
+    out = dict(steps=steps, samples=[], detached_at=None, landed_at=None)
+    thr = 0.5 * (p.rho_l + p.rho_g)
+    dt_steps = 0.0
+    while s.n < steps:
+        s.synchronize()
+        t1 = time.perf_counter()
+        s.step(every)
+        s.synchronize()
+        dt_steps += time.perf_counter() - t1
+        sets = analysis.liquid_sets(s.moments()[0], thr)
+        big = sets[0] if sets else [0, 0.0, 0.0, 0, 0]
+        out["samples"].append(dict(step=int(s.n), liquid_nodes=int(sum(r[0] for r in sets)),
+                                   largest=big[0], largest_y=round(big[1], 1)))
+        if sets and out["detached_at"] is None and big[1] < p.Ny / 2:
+            out["detached_at"] = int(s.n)
+        if sets and out["landed_at"] is None and big[1] < p.Ny / 10:
+            out["landed_at"] = int(s.n)
+    out["mlups"] = round(fluid_nodes(p) * steps / dt_steps / 1e6, 1)
+    s.close()
+    log("gravity plate 100x300: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +390,7 @@ def main():
         extra["mass_run_8192x512"] = large_mass_run()
         extra["d2_law_200x200"] = d2_law_study()
         extra["open_channel_1600x48"] = open_channel_run()
+        extra["gravity_plate_100x300"] = gravity_plate_run()
 
     batched = served = None
     if not args.no_batch:

@@ -87,12 +87,20 @@ enum {
                               are their vapour-branch roots.  Stencils past
                               the ends see the boundary column's own values;
                               the inlet column holds T = T_in.              */
-    LBM_PHASE_PROPS = 128u /* lambda and C_v interpolated between the gas
+    LBM_PHASE_PROPS = 128u, /* lambda and C_v interpolated between the gas
                               values (lambda, C_v) and the liquid values
                               (lambda_l, C_v_l) with the clamped fraction of
                               Eq. 5; the conduction term of Eq. 16 becomes
                               [lambda lap T + grad(lambda).grad(T)] / (rho C_v),
                               solid nodes carrying the gas values           */
+    LBM_TOP_MIXED = 256u   /* Sec. 3.2 plates: the top plate holds T_w on the
+                              columns cold_x0 <= x < cold_x1 and is adiabatic
+                              elsewhere (zero normal gradient at the half-way
+                              wall: a temperature stencil reaching such a
+                              node reads the fluid node below it, at the
+                              same RK stage); the bottom plate holds
+                              T_w_bottom.  Not with LBM_PERIODIC_Y,
+                              LBM_OPEN_X or T_w_end > 0.                    */
 };
 
 /* Parameters, named as in the paper.  lbm_params_default() fills the paper's
@@ -122,10 +130,13 @@ typedef struct {
     double T_in;            /* LBM_OPEN_X inlet temperature; <= 0: T_0          */
     double lambda_l, C_v_l; /* LBM_PHASE_PROPS liquid conductivity and heat
                                capacity (lambda, C_v are then the gas values)    */
+    double T_w_bottom;      /* LBM_TOP_MIXED bottom plate temperature; <= 0: T_0 */
+    int32_t cold_x0, cold_x1; /* LBM_TOP_MIXED cold columns of the top plate,
+                               0 <= cold_x0 <= cold_x1 <= Nx                    */
     int32_t precision;      /* LBM_FP32_DEV, LBM_FP64 or LBM_FP32_DEV_MASSEXACT   */
     uint32_t flags;         /* LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y |
                                LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS |
-                               LBM_OPEN_X | LBM_PHASE_PROPS                      */
+                               LBM_OPEN_X | LBM_PHASE_PROPS | LBM_TOP_MIXED      */
 } lbm_params;
 
 /* Fill *p with the defaults: Nx = 128, Ny = 32, a = 3/49, b = 2/21, R = 1,

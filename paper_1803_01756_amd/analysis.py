@@ -6,17 +6,10 @@ import numpy as np
 from scipy import ndimage
 
 
-def droplets(rho: np.ndarray, threshold: float):
-    """Droplets touching each plate of a channel field rho[y, x] (plate rows
-    included, periodic in x): connected sets (4-neighbour) of fluid nodes with
-    rho > threshold that reach the first fluid row above the lower plate or
-    below the upper plate.  Returns {"bottom": {count, mean_spacing},
-    "top": {...}, "condensed_nodes": n}."""
-    ny, nx = rho.shape
-    liq = rho > threshold
-    liq[0] = liq[-1] = False
+def _periodic_labels(liq: np.ndarray):
+    """4-neighbour labels of a mask, joined across the periodic x boundary."""
+    ny, nx = liq.shape
     lab, n = ndimage.label(liq)
-    # join labels across the periodic x boundary
     parent = list(range(n + 1))
 
     def find(a):
@@ -32,7 +25,39 @@ def droplets(rho: np.ndarray, threshold: float):
             if ra != rb:
                 parent[max(ra, rb)] = min(ra, rb)
     roots = np.array([find(i) for i in range(n + 1)])
-    lab = roots[lab]
+    return roots[lab]
+
+
+def liquid_sets(rho: np.ndarray, threshold: float):
+    """Connected liquid sets of a plate field rho[y, x] (plate rows included,
+    periodic in x), largest first, each as [node count, centroid y, centroid x
+    (circular mean), reaches the row below the top plate, reaches the row
+    above the bottom plate]."""
+    ny, nx = rho.shape
+    liq = rho > threshold
+    liq[0] = liq[-1] = False
+    lab = _periodic_labels(liq)
+    out = []
+    for i in np.unique(lab[lab > 0]):
+        ys, xs = np.nonzero(lab == i)
+        ang = 2 * np.pi * xs / nx
+        cx = (np.arctan2(np.sin(ang).mean(), np.cos(ang).mean()) % (2 * np.pi)) * nx / (2 * np.pi)
+        out.append([int(ys.size), float(ys.mean()), float(cx), int(ys.max() == ny - 2),
+                    int(ys.min() == 1)])
+    out.sort(key=lambda r: -r[0])
+    return out
+
+
+def droplets(rho: np.ndarray, threshold: float):
+    """Droplets touching each plate of a channel field rho[y, x] (plate rows
+    included, periodic in x): connected sets (4-neighbour) of fluid nodes with
+    rho > threshold that reach the first fluid row above the lower plate or
+    below the upper plate.  Returns {"bottom": {count, mean_spacing},
+    "top": {...}, "condensed_nodes": n}."""
+    ny, nx = rho.shape
+    liq = rho > threshold
+    liq[0] = liq[-1] = False
+    lab = _periodic_labels(liq)
     out = {}
     for name, row in (("bottom", 1), ("top", ny - 2)):
         ids = sorted(set(lab[row][lab[row] > 0].tolist()))

@@ -154,3 +154,28 @@ def open_channel(Nx: int = 1600, Ny: int = 48, contact_angle: float = 137.82,
     for k, v in overrides.items():
         setattr(p, "lambda_" if k == "lambda" else k, v)
     return p
+
+
+def gravity_plate(Nx: int = 100, Ny: int = 300, contact_angle: float = 137.82,
+                  Tw_frac: float = 0.65, g: float = 1e-4, cold_band=None,
+                  precision=lbm.LBM_FP32_DEV, **overrides) -> lbm.lbm_params:
+    """Sec. 3.2: saturated vapour at T_sat = 0.86 T_c between two hydrophobic
+    plates, periodic in x, no drive, gravity g toward the bottom plate.  The
+    top plate is cold (Tw_frac T_c) on its central band of columns and
+    adiabatic on either side (flag TOP_MIXED); the bottom plate is held at
+    T_sat.  The band's width is not given (its figure is missing): the
+    default is the middle third, [Nx/3, 2Nx/3).  The contact angle is not
+    given either: the default is the Sec. 3.3 plates' 137.82 degrees."""
+    p = lbm.lbm_params_default(Nx=Nx, Ny=Ny, g_osc=0.0, period=0.0, precision=precision,
+                               flags=lbm.LBM_TOP_MIXED)
+    p = lbm.lbm_params_resolve(p)
+    p.T_w = Tw_frac * p.T_c
+    p.T_w_bottom = p.T_0
+    p.cold_x0, p.cold_x1 = cold_band if cold_band is not None else (Nx // 3, 2 * Nx // 3)
+    p.g_y = -g
+    frac = wall_fraction_for_angle(contact_angle)
+    p.G_w = p.G
+    p.psi_w = lbm.lbm_eos_pressure(p, p.rho_g + frac * (p.rho_l - p.rho_g), p.T_0)[1]
+    for k, v in overrides.items():
+        setattr(p, "lambda_" if k == "lambda" else k, v)
+    return p

@@ -48,6 +48,8 @@ struct Phys {
     double dT_w_end;                    // plate temperature at x = Nx-1 - T_ref
     int wall_ramp;                      // plate temperature linear in x
     double lam_l, cv_l;                 // liquid conductivity and heat capacity
+    double dT_w_bot;                    // bottom plate temperature - T_ref (TOP_MIXED)
+    int cold_x0, cold_x1;               // cold columns of the top plate (TOP_MIXED)
     double rkA, rkB1, rkB2;             // R, a k (1+k)/sqrt(Tc), a k^2 / Tc
     uint32_t flags;                     // LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y
     uint32_t pad_;

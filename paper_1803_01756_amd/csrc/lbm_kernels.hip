@@ -28,7 +28,8 @@
 namespace lbmk {
 namespace {
 
-constexpr uint32_t kFreezeT = 1u, kSinglePhase = 2u, kEosCS = 32u, kPhaseProps = 128u;
+constexpr uint32_t kFreezeT = 1u, kSinglePhase = 2u, kEosCS = 32u, kPhaseProps = 128u,
+                   kTopMixed = 256u;
 
 // ---- lane shifts (DPP wave_shr:1 / wave_shl:1) ---------------------------
 // at_xm(v): the value lane l-1 holds (column x-1); at_xp: lane l+1 (x+1).  The
@@ -639,6 +640,18 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     const R T_ref = kr_.T_ref;
     const R dTw = kr_.dT_wall;
     const R rho_ref = kr_.rho_ref;
+    // Sec. 3.2 plates (TOP_MIXED): the bottom plate holds its own
+    // temperature; the top plate holds T_w on the cold columns and elsewhere
+    // mirrors the fluid row below it, stage by stage (zero normal gradient
+    // at the half-way wall).  plate_t: a plate row's stage value, given the
+    // same stage's value of the row below.
+    const bool top_mixed = kExt && (k.flags & kTopMixed) != 0;
+    const bool adiab = top_mixed && !(cx >= k.cold_x0 && cx < k.cold_x1);
+    auto plate_t = [&](const int y, const R below) {
+        if (!top_mixed) return wall_t();
+        if (y <= 0) return tri_const<R>((R)k.dT_w_bot);
+        return trix(adiab ? below : dTw);
+    };
     const R drive_r = (R)drive;
 
     // ---- register row windows ----
@@ -775,6 +788,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             rhoCur = rho_ref;
             jxCur = jyCur = 0;
             dTA = ramp ? dTw_x : dTw;
+            if (top_mixed) dTA = kr <= 0 ? (R)k.dT_w_bot : (adiab ? tn1.c : dTw);
             psiA = tri_const<double>(k.psi_wall_eff);
         }
         psi0 = psiA;
@@ -884,7 +898,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 acc2 = h1;
                 t1 = trix(tn2.c + (R)0.5 * h1);
             } else {
-                t1 = wall_t();
+                t1 = plate_t(kr - 2, t1b.c);
                 acc2 = 0;
             }
             t1a = t1;
@@ -897,7 +911,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 acc3 += (R)2 * h2;
                 t2 = trix(tn3.c + (R)0.5 * h2);
             } else {
-                t2 = wall_t();
+                t2 = plate_t(kr - 3, t2b.c);
             }
             t2a = t2;
             // ------------- stage E: h3 on row kr-4 ------------------------
@@ -909,7 +923,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 acc4 += (R)2 * h3;
                 t3 = trix(tn4 + h3);
             } else {
-                t3 = wall_t();
+                t3 = plate_t(kr - 4, t3b.c);
             }
             t3a = t3;
             // ------------- stage F: h4 and T(n+1) on row kr-5 -------------
@@ -1089,7 +1103,8 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
         rho_out[i] = 0.0;
         T_out[i] = k.T_ref + (k.wall_ramp ? k.dT_wall + (k.dT_w_end - k.dT_wall) * (double)cx /
                                                               (double)(g.Nx - 1)
-                                          : k.dT_wall);
+                              : ((k.flags & kTopMixed) && y == 0) ? k.dT_w_bot
+                                                                  : k.dT_wall);
         return;
     }
     const unsigned x = (unsigned)cx;
@@ -1291,7 +1306,7 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
 
 bool needs_ext(const Grid& g, const Phys& k) {
     return g.frame_t || g.frame_rho || g.open_x || k.wall_ramp ||
-           (k.flags & (kEosCS | kPhaseProps));
+           (k.flags & (kEosCS | kPhaseProps | kTopMixed));
 }
 
 template <class S, bool kMX>

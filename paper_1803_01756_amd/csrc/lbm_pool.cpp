@@ -283,7 +283,7 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
     for (size_t j = 0; j < act.size(); ++j) {
         SlotState& s = P->slots[act[j]];
         ext = ext || (s.p.flags & (LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS | LBM_OPEN_X |
-                                   LBM_PHASE_PROPS)) ||
+                                   LBM_PHASE_PROPS | LBM_TOP_MIXED)) ||
               s.p.T_w_end > 0.0;
         if (!s.ready_waited) {
             PCHK(hipStreamWaitEvent(P->main, s.ready, 0));

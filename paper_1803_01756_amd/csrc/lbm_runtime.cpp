@@ -268,7 +268,14 @@ lbm_status validate(const lbm_params& p) {
     if (p.Ny < (per ? 3 : 4)) return fail(LBM_EINVAL, "Ny = %d too small", p.Ny);
     if (p.precision < LBM_FP32_DEV || p.precision > LBM_FP32_DEV_MASSEXACT)
         return fail(LBM_EINVAL, "unknown precision %d", p.precision);
-    if (p.flags & ~255u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & ~511u) return fail(LBM_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & LBM_TOP_MIXED) {
+        if (p.flags & (LBM_PERIODIC_Y | LBM_OPEN_X))
+            return fail(LBM_EINVAL, "LBM_TOP_MIXED needs plates and periodic x");
+        if (p.T_w_end > 0.0) return fail(LBM_EINVAL, "LBM_TOP_MIXED excludes T_w_end > 0");
+        if (!(0 <= p.cold_x0 && p.cold_x0 <= p.cold_x1 && p.cold_x1 <= p.Nx))
+            return fail(LBM_EINVAL, "LBM_TOP_MIXED needs 0 <= cold_x0 <= cold_x1 <= Nx");
+    }
     if ((p.flags & LBM_PHASE_PROPS) && !(p.lambda_l >= 0.0 && p.C_v_l > 0.0))
         return fail(LBM_EINVAL, "LBM_PHASE_PROPS needs lambda_l >= 0 and C_v_l > 0");
     if (p.flags & LBM_OPEN_X) {
@@ -415,6 +422,10 @@ void fill_phys(const lbm_params& p, Phys& k) {
     k.lam_l = p.lambda_l;
     k.cv_l = p.C_v_l;
     k.dT_w_end = (p.T_w_end > 0.0 ? p.T_w_end : p.T_w) - p.T_0;
+    k.dT_w_bot = (p.flags & LBM_TOP_MIXED) ? (p.T_w_bottom > 0.0 ? p.T_w_bottom : p.T_0) - p.T_0
+                                           : k.dT_wall;
+    k.cold_x0 = p.cold_x0;
+    k.cold_x1 = p.cold_x1;
     k.rkA = p.R;
     k.rkB1 = p.a * kap * (1.0 + kap) / std::sqrt(p.T_c);
     k.rkB2 = p.a * kap * kap / p.T_c;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "liblbm_hip.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_FP32_DEV, LBM_FP64, LBM_FP32_DEV_MASSEXACT = 0, 1, 2
 LBM_FREEZE_T, LBM_SINGLE_PHASE, LBM_PERIODIC_Y, LBM_FRAME_T, LBM_FRAME_RHO, LBM_EOS_CS = 1, 2, 4, 8, 16, 32
-LBM_OPEN_X, LBM_PHASE_PROPS = 64, 128
+LBM_OPEN_X, LBM_PHASE_PROPS, LBM_TOP_MIXED = 64, 128, 256
 
 _STATUS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EDEVICE: "EDEVICE",
            LBM_EUNSTABLE: "EUNSTABLE", LBM_ESTATE: "ESTATE"}
@@ -50,6 +50,7 @@ class lbm_params(C.Structure):
         ("p_amp", C.c_double), ("p_period", C.c_double),
         ("T_w_end", C.c_double), ("T_in", C.c_double),
         ("lambda_l", C.c_double), ("C_v_l", C.c_double),
+        ("T_w_bottom", C.c_double), ("cold_x0", C.c_int32), ("cold_x1", C.c_int32),
         ("precision", C.c_int32), ("flags", C.c_uint32),
     ]
 

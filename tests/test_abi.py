@@ -62,7 +62,11 @@ def test_library_coexistence_matches_oracle(L, orc, frac):
 
 @pytest.mark.parametrize("bad", [dict(Nx=2), dict(Ny=3), dict(s_e=0.9), dict(s_q=2.0),
                                  dict(tau_g=0.5), dict(G=0.0), dict(precision=7),
-                                 dict(flags=128), dict(flags=256)])
+                                 dict(flags=128), dict(flags=512), dict(flags=256 | 4),
+                                 dict(flags=256 | 64), dict(flags=256, cold_x1=129),
+                                 dict(flags=256, cold_x0=5, cold_x1=3),
+                                 dict(flags=256, cold_x0=-1, cold_x1=3),
+                                 dict(flags=256, T_w_end=0.05)])
 def test_workspace_bytes_rejects_invalid(L, bad):
     p = lbm.lbm_params_default(**bad)
     assert lbm.lbm_workspace_bytes(p) == 0
