@@ -233,12 +233,13 @@ def d2_law_study(N=200, D=60.0, max_steps=320000, every=4000):
             t.append(s.n)
             d.append(analysis.equivalent_diameter(s.moments()[0], p.rho_l, p.rho_g))
         dt = time.perf_counter() - t0
+        n_done = s.n
         s.close()
         ta, d2 = np.array(t, float), (np.array(d) / d[0]) ** 2
         sel = (d2 > 0.2) & (d2 < 0.8)
         K, r2 = analysis.d2_fit(ta[sel], d2[sel]) if sel.sum() >= 3 else (None, None)
-        rec = dict(K=K, R2=None if r2 is None else round(r2, 5), steps=int(s.n),
-                   mlups_incl_readout=round(N * N * s.n / dt / 1e6, 1))
+        rec = dict(K=K, R2=None if r2 is None else round(r2, 5), steps=int(n_done),
+                   mlups_incl_readout=round(N * N * n_done / dt / 1e6, 1))
         if gold:
             ref = [c for c in gold["cases"] if abs(c["lam"] - lam) < 1e-12][0]
             rec["oracle_K"] = ref["K"]
@@ -292,9 +293,9 @@ def gravity_plate_run(steps=40000, every=2500):
     middle third of the top plate at 0.65 T_c, adiabatic sides, bottom plate
     at T_sat, gravity 1e-4 toward it, 137.82 degree plates), FP32: throughput
     and, every `every` steps, the liquid and its largest connected set (node
-    count, centroid height, contact with either plate); the step at which
-    that set leaves the top half, and the one at which it reaches the bottom
-    tenth."""
+    count, centroid height); the first sample at which that set's centroid
+    has left the top tenth of the box (the droplet has come off the cold
+    band), and the first at which it lies in the bottom tenth (landed)."""
     from paper_1803_01756_amd import analysis, configs, lbm
     p = configs.gravity_plate()
     s = lbm.Sim(p, configs.initial_density(p, seed=32))
@@ -311,7 +312,7 @@ def gravity_plate_run(steps=40000, every=2500):
         big = sets[0] if sets else [0, 0.0, 0.0, 0, 0]
         out["samples"].append(dict(step=int(s.n), liquid_nodes=int(sum(r[0] for r in sets)),
                                    largest=big[0], largest_y=round(big[1], 1)))
-        if sets and out["detached_at"] is None and big[1] < p.Ny / 2:
+        if sets and out["detached_at"] is None and big[1] < 0.9 * p.Ny:
             out["detached_at"] = int(s.n)
         if sets and out["landed_at"] is None and big[1] < p.Ny / 10:
             out["landed_at"] = int(s.n)
