@@ -230,7 +230,11 @@ const char* lbm_last_error(void);
 
 /* Checkpoint: lbm_state_bytes() bytes hold the time level, the parameters
  * and the device state; lbm_load() restores a state saved from a simulation
- * with the same grid and precision.  Both synchronise. */
+ * with the same grid and precision (the saved parameters, which must pass
+ * the same checks as lbm_create's, replace the simulation's).  A buffer that
+ * is too small, was written by another version of this format or does not
+ * match gives LBM_EINVAL and leaves the simulation unchanged.  Both
+ * synchronise. */
 size_t lbm_state_bytes(const lbm_sim* sim);
 lbm_status lbm_save(lbm_sim* sim, void* host, size_t bytes);
 lbm_status lbm_load(lbm_sim* sim, const void* host, size_t bytes);

@@ -788,6 +788,10 @@ lbm_status lbm_get_params(const lbm_sim* s, lbm_params* out) {
 
 const char* lbm_last_error(void) { return g_err; }
 
+// Checkpoint magic; the number changes whenever the header (which holds
+// lbm_params) changes layout.
+constexpr char kCkptMagic[9] = "LBMCKPT3";
+
 size_t lbm_state_bytes(const lbm_sim* s) {
     return s ? sizeof(CkptHeader) + state_payload(s) : 0;
 }
@@ -798,7 +802,7 @@ lbm_status lbm_save(lbm_sim* s, void* host, size_t bytes) {
     HIPCHK(hipSetDevice(s->dev));
     CkptHeader h;
     std::memset(&h, 0, sizeof(h));
-    std::memcpy(h.magic, "LBMCKPT2", 8);
+    std::memcpy(h.magic, kCkptMagic, 8);
     h.n = s->n;
     h.p = s->p;
     char* dst = static_cast<char*>(host);
@@ -821,10 +825,11 @@ lbm_status lbm_load(lbm_sim* s, const void* host, size_t bytes) {
     if (bytes < lbm_state_bytes(s)) return fail(LBM_EINVAL, "buffer too small");
     CkptHeader h;
     std::memcpy(&h, host, sizeof(h));
-    if (std::memcmp(h.magic, "LBMCKPT2", 8) != 0) return fail(LBM_EINVAL, "not a checkpoint");
+    if (std::memcmp(h.magic, kCkptMagic, 8) != 0) return fail(LBM_EINVAL, "not a checkpoint");
     if (h.p.Nx != s->p.Nx || h.p.Ny != s->p.Ny || h.p.precision != s->p.precision ||
         (h.p.flags & LBM_PERIODIC_Y) != (s->p.flags & LBM_PERIODIC_Y))
         return fail(LBM_EINVAL, "checkpoint grid or precision differs");
+    if (validate(h.p) != LBM_OK) return LBM_EINVAL;  // message set by validate
     HIPCHK(hipSetDevice(s->dev));
     HIPCHK(hipStreamSynchronize(s->stream));
     const char* src = static_cast<const char*>(host) + sizeof(h);

@@ -133,6 +133,33 @@ def test_checkpoint_roundtrip_bitwise():
         b.close()
 
 
+def test_checkpoint_rejects_foreign_or_invalid():
+    """A checkpoint of another format version, with parameters that fail the
+    creation checks, or cut short is refused with LBM_EINVAL, and the
+    simulation keeps its state."""
+    _case("checkpoint rejection 128x32")
+    p = configs.oracle_size_channel(lbm.LBM_FP32_DEV)
+    a = lbm.Sim(p, configs.initial_density(p, seed=4))
+    a.step(10)
+    blob = a.save()
+    ref = a.moments()
+    old = bytearray(blob)
+    old[7] = ord("2")  # an earlier format version
+    off = 16 + lbm.lbm_params.flags.offset  # header: magic[8], n, params
+    bad = bytearray(blob)
+    bad[off:off + 4] = (1 << 12).to_bytes(4, "little")  # unknown flag
+    try:
+        for b in (bytes(old), bytes(bad), blob[: len(blob) // 2]):
+            with pytest.raises(lbm.LBMError) as ei:
+                a.load(b)
+            assert ei.value.status == lbm.LBM_EINVAL
+        assert a.n == 10
+        for x, y in zip(a.moments(), ref):
+            assert np.array_equal(x, y)
+    finally:
+        a.close()
+
+
 def test_reduce_matches_moments():
     _case("reduce vs moments")
     p = configs.oracle_size_channel()
