@@ -73,6 +73,19 @@ def test_workspace_bytes_rejects_invalid(L, bad):
     assert len(lbm.lib().lbm_last_error()) > 0
 
 
+@pytest.mark.parametrize("prec,bytes_per_node", [(lbm.LBM_FP32_DEV, 80), (lbm.LBM_FP64, 160)])
+def test_workspace_bytes_size_limit(L, prec, bytes_per_node):
+    """The step reaches its buffers by 32-bit byte offsets: a 16384-wide
+    channel is accepted while its step buffers (bytes_per_node per stored
+    node) stay below 4 GiB and refused beyond, without allocating."""
+    rows_max = (1 << 32) // (bytes_per_node * 16384)
+    ok = lbm.lbm_params_default(Nx=16384, Ny=rows_max - 20 + 2, precision=prec)
+    assert lbm.lbm_workspace_bytes(ok) > (rows_max - 20) * 16384 * bytes_per_node
+    big = lbm.lbm_params_default(Nx=16384, Ny=rows_max + 1 + 2, precision=prec)
+    assert lbm.lbm_workspace_bytes(big) == 0
+    assert b"too large" in lbm.lib().lbm_last_error()
+
+
 def test_workspace_bytes_layout(L):
     p = lbm.lbm_params_default(Nx=100, Ny=10)
     n32 = lbm.lbm_workspace_bytes(p)

@@ -95,6 +95,32 @@ def test_full_size_tiled_parity(orc, which):
     assert e["rho"] < 1e-5 and e["u"] < 1e-5 and e["T"] < 1e-5
 
 
+def test_largest_accepted_grid_tiled_parity(orc):
+    """The largest FP32 channel the 32-bit offsets admit at 16384 columns
+    (step buffers just below 4 GiB): the same tiled start, 10 steps, every
+    128-column tile bitwise equal and one tile against the oracle.  The top
+    rows' buffer offsets come within a few MB of 2^32."""
+    rows = (1 << 32) // (80 * 16384)
+    p = configs.channel_params(16384, rows + 2, 75.0, 0.78, 2e-6, 4000.0, lbm.LBM_FP32_DEV)
+    assert lbm.lbm_workspace_bytes(p) > 0
+    _case("largest grid 16384x%d fp32, tiled start, 10 steps" % p.Ny)
+    tile = 128
+    r_tile = inputs.density_field(tile, p.Ny, p.rho_v, 0.01, 6)
+    s = lbm.Sim(p, np.tile(r_tile, (1, p.Nx // tile)))
+    s.step(10)
+    g = s.moments()
+    s.close()
+    for a in g:
+        t0 = a[:, :tile]
+        for k in range(1, p.Nx // tile):
+            assert np.array_equal(a[:, k * tile:(k + 1) * tile], t0), k
+    q = lbm.lbm_params.from_buffer_copy(p)
+    q.Nx = tile
+    e = field_errors([a[:, :tile] for a in g], _oracle(orc, q, r_tile, 10), fluid_mask(tile, p.Ny))
+    print(e, flush=True)
+    assert e["rho"] < 1e-5 and e["u"] < 1e-5 and e["T"] < 1e-5
+
+
 def test_mass_exact_storage_conserves_mass():
     _case("mass drift 256x64, 3000 steps")
     drift = {}
