@@ -258,10 +258,11 @@ def open_channel_run(steps=6000, every=2000):
     oscillating-pressure inlet, constant-pressure outlet, plates 0.86 -> 0.56
     T_c, gravity +x, 137.82 degree plates), FP32: throughput and the
     condensate (liquid nodes, droplets on the plates) every `every` steps.
-    The run stops at 6000 steps: with the outlet held at the saturation
-    pressure of 0.86 T_c, the vapour entering at the cold outlet corners
-    reaches |u| ~ 0.3 and the state turns non-finite between steps 6000 and
-    8000 (FP32 and FP64 alike, and the oracle on a shortened channel)."""
+    The run stops at 6000 steps: condensation thins the vapour at the cold
+    end until lambda / (rho C_v) passes the stability bound of the energy
+    equation's explicit RK4 (0.522 for the nine-point Laplacian, rho below
+    0.096), near step 6100, and the state diverges by step 6500 (FP32 and
+    FP64 alike, and the oracle on a shortened channel)."""
     from paper_1803_01756_amd import analysis, configs, lbm
     p = configs.open_channel()
     s = lbm.Sim(p, configs.initial_density(p, seed=1))
