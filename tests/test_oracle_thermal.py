@@ -256,3 +256,25 @@ def test_phase_props_conduction_exact_on_polynomials(orc):
     expect = (2 * bT * lam + a * 2 * bT * x) / (rho * cv)
     inner = (slice(None), slice(1, -1))
     np.testing.assert_allclose(K[inner], expect[inner], rtol=1e-10)
+
+
+@pytest.mark.parametrize("D", [0.50, 0.55])
+def test_rk4_stability_bound_on_checkerboard(orc, D):
+    """The checkerboard mode (-1)^(x+y) is the nine-point Laplacian's extreme
+    eigenvector (eigenvalue -16/3), so the step multiplies it by R(-16 D / 3)
+    with D = lambda / (rho C_v): it decays for D below 2.785 * 3 / 16 = 0.522
+    and grows above; the stated bound on the thin-vapour stability follows."""
+    Nx = Ny = 8
+    rho, Cv = 0.4, 5.0
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y | orc.SINGLE_PHASE,
+                           period=0.0, lam=D * rho * Cv, Cv=Cv)
+    s = orc.Sim(p, rho_uniform=rho)
+    x, y = _grid(Nx, Ny)
+    mode = (-1.0) ** (x + y)
+    eps = 1e-6 * p.T0
+    s.set_T(p.T0 + eps * mode)
+    s.step(10)
+    T = s.moments()[3]
+    r = _rk4_factor(-16.0 * D / 3.0)
+    np.testing.assert_allclose(T, p.T0 + eps * r ** 10 * mode, rtol=0, atol=1e-12 * p.T0)
+    assert (abs(r) < 1) == (D < 0.522)
