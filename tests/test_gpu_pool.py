@@ -58,6 +58,44 @@ def test_pool_staggered_admission_equals_alone():
     pool.close()
 
 
+def test_pool_mixed_features_equal_alone():
+    """One batch holding a plain channel and channels with each optional
+    feature (Sec. 3.2 plates, phase-dependent properties, Carnahan-Starling,
+    open ends, a held reservoir frame): a feature in any slot makes the whole
+    batch run the kernel build with the optional features, and every slot,
+    the plain one included, still gives bitwise its result alone."""
+    _case("pool with optional features")
+    prec = lbm.LBM_FP32_DEV
+    plain = _chan(200, 30, 110.0, 0.80, 2e-6, 300.0, 11)
+    grav = configs.gravity_plate(90, 40, cold_band=(30, 60), precision=prec)
+    props = configs.channel_params(120, 26, 90.0, 0.78, 2e-5, 200.0, prec, lbm.LBM_PHASE_PROPS,
+                                   lambda_l=0.6, C_v_l=3.0)
+    cs = configs.channel_params_cs(96, 24, 0.45, 0.8, 1e-4, 400.0, prec)
+    opn = configs.open_channel(131, 24, p_period=300.0, precision=prec)
+    box = configs.d2_box(1.0 / 3.0, prec, N=60)
+    chans = [plain, (grav, configs.initial_density(grav, 12)),
+             (props, configs.initial_density(props, 13)), (cs, configs.initial_density(cs, 14)),
+             (opn, configs.initial_density(opn, 15)), (box, configs.droplet_density(box, 20.0))]
+    steps = [300, 260, 220, 280, 240, 200]
+    pool = lbm.Pool(1 << 30)
+    sl = [pool.admit(p, r0, n) for (p, r0), n in zip(chans, steps)]
+    done = set()
+    for _ in range(20):
+        pool.run(100)
+        pool.wait(0)
+        done |= set(pool.poll())
+        if len(done) == len(sl):
+            break
+    assert done == set(sl)
+    for (p, r0), s, n in zip(chans, sl, steps):
+        assert pool.slot_time(s) == n
+        got = pool.moments(s, p.Nx, p.Ny)
+        ref = _alone(p, r0, n)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+    pool.close()
+
+
 def test_pool_admission_by_footprint():
     _case("pool cap")
     a, b = _chan(256, 32, 120.0, 0.8, 1e-6, 500.0, 5), _chan(512, 64, 120.0, 0.8, 1e-6, 500.0, 6)
