@@ -55,7 +55,7 @@ def test_edge_grids_fp64(orc, Nx, Ny):
                                    lbm.LBM_FRAME_T, lbm.LBM_FRAME_T | lbm.LBM_PERIODIC_Y,
                                    lbm.LBM_FRAME_RHO,
                                    lbm.LBM_FRAME_T | lbm.LBM_FRAME_RHO | lbm.LBM_PERIODIC_Y])
-@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 def test_flags_parity(orc, flags, precision):
     _case("flags=%d precision=%d 60x20" % (flags, precision))
     extra = {}
@@ -244,7 +244,7 @@ def test_parity_2000_steps(orc, precision):
         assert e["rho"] < 1e-4 and e["u"] < 1e-3 and e["T"] < 1e-4
 
 
-@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 @pytest.mark.parametrize("flags", [0, lbm.LBM_PERIODIC_Y])
 def test_cs_eos_parity(orc, precision, flags):
     """The Carnahan-Starling option (a = 1, b = 4, R = 1) on a 96 x 24 channel
@@ -263,7 +263,7 @@ def test_cs_eos_parity(orc, precision, flags):
     assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
 
 
-@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 @pytest.mark.parametrize("Nx,Ny", [(60, 20), (131, 24)])
 def test_open_channel_parity(orc, precision, Nx, Ny):
     """Sec. 3.3 boundary set (OPEN_X): Zou-He oscillating-pressure inlet and
@@ -279,7 +279,7 @@ def test_open_channel_parity(orc, precision, Nx, Ny):
     assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
 
 
-@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 def test_phase_props_parity(orc, precision):
     """Phase-dependent conductivity and heat capacity (PHASE_PROPS: lambda
     0.25 -> 0.6, C_v 5 -> 3 from gas to liquid) on the cold-plate channel
@@ -302,7 +302,7 @@ def test_phase_props_parity(orc, precision):
     assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
 
 
-@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 @pytest.mark.parametrize("Nx,Ny,band", [(80, 40, (26, 53)), (131, 24, (40, 70)),
                                         (60, 20, (0, 17)), (70, 16, (0, 0))])
 def test_top_mixed_parity(orc, precision, Nx, Ny, band):
