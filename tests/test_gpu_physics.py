@@ -304,14 +304,17 @@ def test_phase_props_parity(orc, precision):
 
 @pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 @pytest.mark.parametrize("Nx,Ny,band", [(80, 40, (26, 53)), (131, 24, (40, 70)),
-                                        (60, 20, (0, 17)), (70, 16, (0, 0))])
+                                        (60, 20, (0, 17)), (70, 16, (0, 0)), (72, 18, (20, 50))])
 def test_top_mixed_parity(orc, precision, Nx, Ny, band):
     """Sec. 3.2 plates (TOP_MIXED): a cold band on the top plate, adiabatic
     elsewhere, the bottom plate at T_sat, gravity toward the bottom, 200
     steps against the oracle.  The bands cross a 54-column strip boundary,
-    start at column 0, or are empty (an adiabatic top plate)."""
+    start at column 0, or are empty (an adiabatic top plate); one case also
+    holds the outermost columns (FRAME_T)."""
     _case("top mixed %dx%d band %s precision=%d, 200 steps" % (Nx, Ny, band, precision))
     p = configs.gravity_plate(Nx, Ny, cold_band=band, precision=precision)
+    if Nx == 72:  # with the outermost columns held as well (FRAME_T)
+        p.flags |= lbm.LBM_FRAME_T
     rho0 = configs.initial_density(p, seed=Nx + Ny)
     e = field_errors(_gpu(p, rho0, 200), _oracle(orc, p, rho0, 200), fluid_mask(Nx, Ny))
     print(e, flush=True)

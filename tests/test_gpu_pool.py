@@ -96,6 +96,22 @@ def test_pool_mixed_features_equal_alone():
     pool.close()
 
 
+def test_pool_refuses_other_precisions():
+    """Slots hold FP32 deviations only: FP64 and mass-exact requests are
+    refused with LBM_EINVAL and leave the pool empty."""
+    _case("pool precision check")
+    pool = lbm.Pool(1 << 28)
+    try:
+        for prec in (lbm.LBM_FP64, lbm.LBM_FP32_DEV_MASSEXACT):
+            p = configs.channel_params(64, 20, 90.0, 0.8, 1e-6, 500.0, prec)
+            with pytest.raises(lbm.LBMError) as ei:
+                pool.admit(p, configs.initial_density(p, 1), 10)
+            assert ei.value.status == lbm.LBM_EINVAL
+        assert pool.poll() == []
+    finally:
+        pool.close()
+
+
 def test_pool_admission_by_footprint():
     _case("pool cap")
     a, b = _chan(256, 32, 120.0, 0.8, 1e-6, 500.0, 5), _chan(512, 64, 120.0, 0.8, 1e-6, 500.0, 6)
