@@ -15,6 +15,12 @@ follows from where that circle meets the wall plane y = 1/2:
 cos(theta) = (1/2 - y_c) / R.  A droplet whose lowest interface point lies
 more than 4 rows above the plate has left it and counts as 180 degrees.
 
+Parity unpinned: the one angle the paper prints (137.82 degrees for G_w = 0.2
+in Sec. 3.3) cannot be reproduced from what it states (psi at the wall, G and
+the way the angle was measured are not given), so this table is the build's
+own calibration, checked only for the monotone trend of angle with wall
+potential.
+
     python oracle/calibrate_contact_angle.py [fractions...]
 """
 import json

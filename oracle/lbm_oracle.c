@@ -21,6 +21,8 @@
  *    derivative of those moments.
  *  - Eq. 8: the eighth source entry is u_x F_y + u_y F_x and the theta term of
  *    the third entry enters with a minus sign (mirrors the e/epsilon pair).
+ *    The epsilon moment is non-hydrodynamic, so no test tells the printed
+ *    sign from this one: fidelity of that sign is unpinned.
  *  - Eq. 5: denominator rho_l - rho_g, fraction clamped to [0, 1].
  *  - Eq. 14: the adhesion sum runs over SOLID neighbours with the wall value
  *    psi_w; the fluid-fluid sum of Eq. 9 runs over fluid neighbours.
