@@ -160,3 +160,40 @@ def test_cs_eos_matches_oracle(orc):
     for rho in (0.02, 0.13, 0.3):
         P, psi = lbm.lbm_eos_pressure(p, rho, 0.8 * tc)
         assert P == pytest.approx(orc.peos(q, rho, 0.8 * tc), rel=1e-13)
+
+
+def test_null_handles_are_refused_without_a_device(L):
+    """Every entry point that takes a simulation or pool handle refuses a
+    null one with LBM_EINVAL (destroy accepts it) before touching the GPU;
+    this runs on a machine without one."""
+    import ctypes as C
+    f = lbm.lib()
+    d = C.c_double()
+    i32 = C.c_int32()
+    EINVAL = lbm.LBM_EINVAL
+    assert f.lbm_step(None, 1) == EINVAL
+    assert f.lbm_moments(None, None, None, None, None) == EINVAL
+    assert f.lbm_reduce(None, C.byref(d)) == EINVAL
+    assert f.lbm_synchronize(None) == EINVAL
+    assert f.lbm_destroy(None) == lbm.LBM_OK
+    assert f.lbm_time(None) == -1
+    assert f.lbm_get_params(None, C.byref(lbm.lbm_params())) == EINVAL
+    assert f.lbm_state_bytes(None) == 0
+    assert f.lbm_save(None, None, 0) == EINVAL
+    assert f.lbm_load(None, None, 0) == EINVAL
+    assert f.lbm_set_launch(None, 26) == EINVAL
+    assert f.lbm_get_launch(None, C.byref(i32), C.byref(i32)) == EINVAL
+    assert f.lbm_autotune(None, 3, C.byref(d)) == EINVAL
+    assert f.lbm_pool_admit(None, C.byref(lbm.lbm_params_default()), None, 10, C.byref(i32)) == EINVAL
+    assert f.lbm_pool_run(None, 10) == EINVAL
+    assert f.lbm_pool_wait(None, 0) == EINVAL
+    assert f.lbm_pool_poll(None, None, 0, C.byref(i32)) == EINVAL
+    assert f.lbm_pool_moments(None, 0, None, None, None, None) == EINVAL
+    assert f.lbm_pool_release(None, 0) == EINVAL
+    assert f.lbm_pool_destroy(None) == lbm.LBM_OK
+    assert f.lbm_pool_info(None, None, None, None) == EINVAL
+    assert f.lbm_pool_slot_time(None, 0) == -1
+    assert f.lbm_pool_set_launch(None, 26) == EINVAL
+    assert f.lbm_pool_synchronize(None) == EINVAL
+    assert f.lbm_pool_create(0, None, None) == EINVAL
+    assert len(f.lbm_last_error()) > 0
