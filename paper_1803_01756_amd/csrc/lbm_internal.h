@@ -109,7 +109,9 @@ struct Slot {
 
 // Step i of a chunk over every slot of the table (slots sorted by
 // unit_begin, total_units = sum of their units).
-// ext: some slot uses an optional feature (FRAME_T, FRAME_RHO, EOS_CS)
+// ext: some slot uses an optional feature (frames, Carnahan-Starling EOS,
+// open ends, plate temperature ramp, phase-dependent properties, Sec. 3.2
+// plates), so the batch runs the kernel build that has them
 hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, int step_i, bool ext,
                                hipStream_t s);
 

@@ -268,8 +268,8 @@ __device__ __forceinline__ double sqrt_d(double x) {
 // error, not a neighbour difference); the FP64 build takes it in FP64.
 // The Carnahan-Starling option (flag kEosCS), e = b rho / 4:
 //   P = rho R T (1 + e + e^2 - e^3) / (1 - e)^3 - a rho^2.
-// kExt: the build that also serves the optional features (Carnahan-Starling
-// EOS, box frames); the plain build leaves their code out.
+// kExt: the build that also serves the optional features (here the
+// Carnahan-Starling EOS); the plain build leaves their code out.
 template <bool kF32, bool kExt = true>
 __device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k) {
     constexpr int kNewton = kF32 ? 1 : 2;
@@ -557,9 +557,11 @@ __device__ __forceinline__ int unit_of_block(int nblocks_pad) {
 }
 
 // One wave's share of a step: the strip and row segment of `unit`.  kExt
-// compiles in the optional features (FRAME_T, FRAME_RHO, EOS_CS); the plain
-// instantiation, used whenever none is set, keeps the register budget of
-// three waves per SIMD.
+// compiles in the optional features (held and reservoir frames, the
+// Carnahan-Starling EOS, open ends and plate temperature ramps,
+// phase-dependent conductivity and heat capacity, the Sec. 3.2 plates); the
+// plain instantiation, used whenever none is set, keeps the register budget
+// of three waves per SIMD.
 template <class S, bool kMX, bool kExt>
 __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bufs<S>& B,
                                           double drive, double rho_in, int unit) {
