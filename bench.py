@@ -114,7 +114,9 @@ def oracle_mlups(p, rho0, steps):
 def batch_and_serve(args):
     """64 channels of uneven size in one pool vs the same channels run one
     after another alone; then a Poisson stream of requests served with
-    continuous batching."""
+    continuous batching, under a cap that never binds and again under one
+    (256 MiB) that makes requests wait for admission."""
+    import numpy as np
     from paper_1803_01756_amd import inputs, lbm, serve
     chans = [serve.channel_request(d, args.batch_steps)
              for d in inputs.sample_channels(64, seed=1803)]
@@ -144,6 +146,22 @@ def batch_and_serve(args):
                   mean_latency_s=round(st["mean_s"], 4), sims_per_s=round(st["sims_per_s"], 3),
                   mlups=round(lu / st["span_s"] / 1e6, 1))
     log("served p50 %.3f s p99 %.3f s, %.2f sims/s" % (st["p50_s"], st["p99_s"], st["sims_per_s"]))
+    # the same stream under a cap that binds: requests wait for admission
+    cap = 256 << 20
+    reqs = serve.make_requests(args.serve_requests, args.serve_rate)
+    log("served again under a %d MiB cap" % (cap >> 20))
+    pool = lbm.Pool(cap)
+    serve.serve(reqs, pool, chunk=500)
+    pool.close()
+    meas = reqs[n_warm:]
+    st = serve.latency_stats(meas)
+    wait = np.array([r.admitted - r.arrival for r in meas])
+    served["capped"] = dict(cap_bytes=cap, p50_latency_s=round(st["p50_s"], 4),
+                            p99_latency_s=round(st["p99_s"], 4),
+                            mean_admission_wait_s=round(float(wait.mean()), 4),
+                            max_admission_wait_s=round(float(wait.max()), 4),
+                            sims_per_s=round(st["sims_per_s"], 3))
+    log("capped: %s" % served["capped"])
     return batched, served
 
 

@@ -114,6 +114,9 @@ def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.per
             r = queue[0]
             slot = pool.admit(r.params, r.rho0, r.steps)
             if slot is None:
+                if not by_slot:  # an empty pool cannot hold it: it never will
+                    raise ValueError("request of %dx%d needs more than the pool's cap"
+                                     % (r.params.Nx, r.params.Ny))
                 break
             queue.popleft()
             r.slot, r.admitted = slot, clock() - t0

@@ -2,6 +2,7 @@
 reuse, completion order, latency accounting) against a fake pool with a
 scripted cost per chunk and a simulated clock: no GPU involved."""
 import numpy as np
+import pytest
 
 from paper_1803_01756_amd import serve
 
@@ -118,3 +119,14 @@ def test_late_arrivals_join_a_running_batch():
     serve.serve(reqs, pool, chunk=500, clock=clk, sleep=clk.sleep)
     assert reqs[1].admitted < reqs[0].finished
     assert reqs[1].finished < reqs[0].finished
+
+
+def test_request_larger_than_the_cap_is_refused():
+    """A request that does not fit an empty pool can never be admitted: the
+    loop raises instead of waiting for room that will not come."""
+    clk = FakeClock()
+    pool = FakePool(cap=1000, clock=clk)
+    reqs = [serve.Request(0, 0.0, FakeParams(10, 10), None, 100),
+            serve.Request(1, 0.01, FakeParams(100, 100), None, 100)]
+    with pytest.raises(ValueError):
+        serve.serve(reqs, pool, chunk=50, clock=clk, sleep=clk.sleep)
