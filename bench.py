@@ -320,6 +320,7 @@ def open_channel_wettability(steps=5000, every=1000, angles=(115.0, 145.0)):
     for ang in angles:
         p = configs.open_channel(contact_angle=ang)
         s = lbm.Sim(p, configs.initial_density(p, seed=1))
+        s.autotune(3)
         thr = 0.5 * (p.rho_l + p.rho_g)
         liq = []
         while s.n < steps:
@@ -349,7 +350,8 @@ def gravity_plate_run(steps=40000, every=2500):
     from paper_1803_01756_amd import analysis, configs, lbm
     p = configs.gravity_plate()
     s = lbm.Sim(p, configs.initial_density(p, seed=32))
-    out = dict(steps=steps, samples=[], detached_at=None, landed_at=None)
+    s.autotune(3)
+    out = dict(steps=steps, samples=[], detached_at=None, landed_at=None, seg_rows=s.launch()[0])
     thr = 0.5 * (p.rho_l + p.rho_g)
     dt_steps = 0.0
     while s.n < steps:

@@ -14,7 +14,8 @@
  *   - classical RK4 of the energy equation (Eqs. 16-18) with isotropic
  *     nine-point finite differences,
  *   - streaming (Eq. 12) with half-way bounce-back at the plates.
- * The plates are the solid rows y = 0 and y = Ny-1; x is periodic.
+ * The plates are the solid rows y = 0 and y = Ny-1 and x is periodic, unless
+ * a flag below (LBM_PERIODIC_Y, LBM_OPEN_X) says otherwise.
  *
  * Conventions for every entry point:
  *   - Status codes only; nothing throws or exits.  On failure an output
