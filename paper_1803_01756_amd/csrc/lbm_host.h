@@ -24,7 +24,7 @@ struct Layout {
 lbm_status fail(lbm_status st, const char* fmt, ...);
 bool make_layout(const lbm_params& p, Layout* L);
 lbm_status validate(const lbm_params& p);
-int default_seg_rows(const lbm_params& p, int rows);
+int default_seg_rows(const lbm_params& p, int rows, int min_rows = 2);
 void fill_grid(const lbm_params& p, const Layout& L, int seg_rows, lbmk::Grid& g);
 void fill_phys(const lbm_params& p, lbmk::Phys& k);
 

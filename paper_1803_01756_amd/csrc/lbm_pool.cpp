@@ -115,7 +115,9 @@ SlotState* get_slot(lbm_pool* P, int32_t id) {
 
 int seg_rows_for(const lbm_pool* P, const SlotState& s) {
     if (P->seg_cap > 0) return std::min(P->seg_cap, s.L.rows);
-    return lbmhost::default_seg_rows(s.p, s.L.rows);
+    // many channels share one launch, so each keeps segments of at least
+    // 14 rows rather than aiming at a full round of waves by itself
+    return lbmhost::default_seg_rows(s.p, s.L.rows, 14);
 }
 
 }  // namespace

@@ -347,13 +347,13 @@ namespace lbmhost {
 // default launch shape: enough waves to give each of the 1024 SIMDs about two
 // (the register budget of the fused kernel allows two resident per SIMD), but
 // segments of at least 16 rows so the 10 recomputed halo rows stay a minority.
-int default_seg_rows(const lbm_params& p, int rows) {
+int default_seg_rows(const lbm_params& p, int rows, int min_rows) {
     const int strips = (p.Nx + lbmk::kOwned - 1) / lbmk::kOwned;
     // one resident round: 256 CUs x 4 SIMDs x 3 waves (the FP32 budget)
     const int want_units = 3072;
     int segs = std::max(1, (want_units + strips - 1) / strips);
     int sr = (rows + segs - 1) / segs;
-    sr = std::max(sr, 14);
+    sr = std::max(sr, min_rows);
     sr = sr + (6 - (sr + 10) % 6) % 6;  // seg + 10 a multiple of the 6-row unroll
     return std::min(sr, rows);
 }
