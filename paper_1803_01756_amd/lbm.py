@@ -316,6 +316,7 @@ class Sim:
         self.Nx, self.Ny = self.params.Nx, self.params.Ny
 
     def step(self, n: int = 1):
+        """Enqueue n steps (lbm_step); returns before they run."""
         lbm_step(self.h, n)
 
     def moments(self):
@@ -323,31 +324,44 @@ class Sim:
         return lbm_moments(self.h, self.Nx, self.Ny)
 
     def reduce(self, check: bool = True):
+        """FP64 totals of the fluid nodes (lbm_reduce); with check, a
+        non-finite state raises LBMError(LBM_EUNSTABLE)."""
         return lbm_reduce(self.h, check)
 
     def synchronize(self):
+        """Wait for the enqueued steps (lbm_synchronize)."""
         lbm_synchronize(self.h)
 
     @property
     def n(self) -> int:
+        """Current time level (lbm_time)."""
         return lbm_time(self.h)
 
     def save(self) -> bytes:
+        """Checkpoint of the time level, parameters and state (lbm_save)."""
         return lbm_save(self.h)
 
     def load(self, blob: bytes):
+        """Restore a checkpoint of a channel of the same grid and precision
+        (lbm_load)."""
         lbm_load(self.h, blob)
 
     def set_launch(self, seg_rows: int):
+        """Rows per wave of the step kernel; <= 0 restores the default
+        (lbm_set_launch).  Results do not depend on it."""
         lbm_set_launch(self.h, seg_rows)
 
     def launch(self):
+        """(seg_rows, waves) of the current launch shape (lbm_get_launch)."""
         return lbm_get_launch(self.h)
 
     def autotune(self, steps_per_trial: int = 10) -> float:
+        """Time candidate launch shapes on this channel, keep the fastest and
+        restore the state (lbm_autotune); returns its ms per step."""
         return lbm_autotune(self.h, steps_per_trial)
 
     def close(self):
+        """Free the simulation (lbm_destroy); idempotent."""
         if getattr(self, "h", None):
             lbm_destroy(self.h)
             self.h = None
@@ -385,6 +399,8 @@ class Pool:
         self.h = h.value
 
     def admit(self, p: lbm_params, rho0, nsteps: int):
+        """Admit a channel for nsteps steps (lbm_pool_admit): its slot id,
+        or None while its footprint does not fit under the cap."""
         r = None if rho0 is None else np.ascontiguousarray(rho0, dtype=np.float64)
         slot = C.c_int32()
         st = lib().lbm_pool_admit(C.c_void_p(self.h), C.byref(p), _dp(r), int(nsteps),
@@ -395,40 +411,52 @@ class Pool:
         return slot.value
 
     def run(self, chunk_steps: int):
+        """Enqueue up to chunk_steps steps of every unfinished slot
+        (lbm_pool_run)."""
         _check(lib().lbm_pool_run(C.c_void_p(self.h), int(chunk_steps)))
 
     def poll(self, max_n: int = 1024):
+        """Slots that finished since the last poll (lbm_pool_poll)."""
         buf = (C.c_int32 * max_n)()
         n = C.c_int32()
         _check(lib().lbm_pool_poll(C.c_void_p(self.h), buf, max_n, C.byref(n)))
         return list(buf[:n.value])
 
     def moments(self, slot: int, Nx: int, Ny: int):
+        """(rho, ux, uy, T) of a slot as float64 [Ny, Nx] arrays
+        (lbm_pool_moments)."""
         outs = [np.empty((Ny, Nx)) for _ in range(4)]
         _check(lib().lbm_pool_moments(C.c_void_p(self.h), int(slot), *[_dp(o) for o in outs]))
         return tuple(outs)
 
     def release(self, slot: int):
+        """Free a slot's memory for later admissions (lbm_pool_release)."""
         _check(lib().lbm_pool_release(C.c_void_p(self.h), int(slot)))
 
     def info(self):
+        """(active slots, bytes used, cap bytes) (lbm_pool_info)."""
         a, u, c = C.c_int32(), C.c_size_t(), C.c_size_t()
         _check(lib().lbm_pool_info(C.c_void_p(self.h), C.byref(a), C.byref(u), C.byref(c)))
         return a.value, u.value, c.value
 
     def slot_time(self, slot: int) -> int:
+        """Time level a slot has reached, -1 for no such slot."""
         return int(lib().lbm_pool_slot_time(C.c_void_p(self.h), int(slot)))
 
     def set_launch(self, seg_rows: int):
+        """Rows per wave for every slot; <= 0: per-slot default."""
         _check(lib().lbm_pool_set_launch(C.c_void_p(self.h), int(seg_rows)))
 
     def synchronize(self):
+        """Wait for every enqueued chunk."""
         _check(lib().lbm_pool_synchronize(C.c_void_p(self.h)))
 
     def wait(self, max_pending: int):
+        """Block until at most max_pending chunks are still running."""
         _check(lib().lbm_pool_wait(C.c_void_p(self.h), int(max_pending)))
 
     def close(self):
+        """Free the pool and every slot (lbm_pool_destroy); idempotent."""
         if getattr(self, "h", None):
             lib().lbm_pool_destroy(C.c_void_p(self.h))
             self.h = None
