@@ -479,7 +479,10 @@ def main():
                      "traffic": None if traffic is None else round(traffic),
                      "bytes_per_lup": BYTES_PER_LUP[0],
                      "copy_probe_gbs": round(probe_gbs, 1),
-                     "frac_of_copy_probe": round(achieved / probe_gbs, 4)},
+                     "frac_of_copy_probe": round(achieved / probe_gbs, 4),
+                     # HBM bytes the counters saw per launch, over the same time
+                     "counter_gbs": None if traffic is None else round(traffic / (ms_step * 1e-3) / 1e9, 1),
+                     "counter_frac": None if traffic is None else round(traffic / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
         "wall_ms_timed": round(wall_ms, 3),
         "mass": red[0],
