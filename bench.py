@@ -43,6 +43,20 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def host_info():
+    """Logical CPUs and CPU model of the host the CPU baseline ran on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), model=model)
+
+
 def kernel_sha():
     with open(KERNEL_SRC, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
@@ -456,10 +470,11 @@ def main():
         cm, dt = oracle_mlups(p, rho0, args.cpu_steps)
         cpu = dict(value=round(cm, 3), unit="MLUPS", cores=1, kind="oracle",
                    sample="FP64 oracle, single thread, %d steps of the full 8192x512 grid "
-                          "(%.1f s)" % (args.cpu_steps, dt))
+                          "(%.1f s)" % (args.cpu_steps, dt),
+                   host=host_info())
 
     line = {
-        "metric": "MLUPS (fused FP32 step, 8192x512 channel) & % HBM roofline",
+        "metric": "MLUPS & % HBM roofline (FP32 fused step); batched sims/s + p50/p99 latency",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
