@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from helpers import field_errors, fluid_mask, to_oracle
-from paper_1803_01756_amd import configs, lbm
+from paper_1803_01756_amd import configs, inputs, lbm
 
 pytestmark = pytest.mark.gpu
 
@@ -58,3 +58,23 @@ def test_launch_shapes_bitwise_identical():
         out = _run_gpu(p, rho0, 25, seg_rows=sr)
         for a, b in zip(out, ref):
             assert np.array_equal(a, b), sr
+
+
+@pytest.mark.parametrize("precision", [lbm.LBM_FP32_DEV, lbm.LBM_FP64, lbm.LBM_FP32_DEV_MASSEXACT])
+def test_gravity_two_phase_launch_shapes_and_oracle(orc, precision):
+    """A two-phase plate channel with gravity along y (no optional feature):
+    every launch shape gives the bits of one segment spanning the channel,
+    and the fields match the oracle after 200 steps."""
+    _case("gravity 256x130 two-phase precision=%d 200 steps" % precision)
+    p = configs.channel_params(256, 130, 120.0, 0.8, 1e-5, 100.0, precision, 0, g_y=-2e-5)
+    rho0 = inputs.density_field(256, 130, p.rho_v, 0.01, 7)
+    ref = _run_gpu(p, rho0, 200, seg_rows=128)  # one segment
+    for sr in (2, 8, 14, 26):
+        out = _run_gpu(p, rho0, 200, seg_rows=sr)
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b), sr
+    r = _run_oracle(orc, p, rho0, 200)
+    e = field_errors(ref, r, fluid_mask(p.Nx, p.Ny))
+    print(e, flush=True)
+    tol = (1e-10, 1e-8, 1e-10) if precision == lbm.LBM_FP64 else (1e-5, 1e-5, 1e-5)
+    assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
