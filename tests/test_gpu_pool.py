@@ -7,7 +7,8 @@ differs.  Admission must respect the byte cap."""
 import numpy as np
 import pytest
 
-from paper_1803_01756_amd import configs, lbm, serve
+from helpers import field_errors, fluid_mask, to_oracle
+from paper_1803_01756_amd import configs, inputs, lbm, serve
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +95,31 @@ def test_pool_mixed_features_equal_alone():
         for a, b in zip(got, ref):
             assert np.array_equal(a, b)
     pool.close()
+
+
+def test_sampled_batch_channels_match_oracle(orc):
+    """The eight smallest channels of the batched workload's draw (seed 1803:
+    uneven sizes, contact angles 80-146 degrees, wall temperatures
+    0.76-0.83 Tc, different drive periods and amplitudes), stepped together
+    in one pool: each matches the oracle within 1e-5 after 100 steps."""
+    _case("sampled batch channels vs oracle, 100 steps")
+    draws = sorted(inputs.sample_channels(64, 1803), key=lambda d: d["Nx"] * d["Ny"])[:8]
+    chans = [serve.channel_request(d, 100) for d in draws]
+    pool = lbm.Pool(1 << 30)
+    try:
+        slots = [pool.admit(p, r0, 100) for p, r0 in chans]
+        assert None not in slots
+        pool.run(100)
+        pool.wait(0)
+        for (p, r0), s in zip(chans, slots):
+            got = pool.moments(s, p.Nx, p.Ny)
+            o = orc.Sim(to_oracle(orc, p), r0)
+            o.step(100)
+            e = field_errors(got, o.moments(), fluid_mask(p.Nx, p.Ny))
+            print(p.Nx, p.Ny, e, flush=True)
+            assert e["rho"] < 1e-5 and e["u"] < 1e-5 and e["T"] < 1e-5
+    finally:
+        pool.close()
 
 
 def test_pool_refuses_other_precisions():
