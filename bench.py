@@ -35,7 +35,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {0: 80.0, 1: 160.0, 2: 88.0}  # FP32_DEV, FP64, FP32_DEV_MASSEXACT
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_step_8192x512_fp32.json")
+# headline storage: name -> (lbm precision code, dtype label, description, profile tag)
+PRECISIONS = {"fp32": (0, "f32", "FP32 deviation storage", "fp32"),
+              "fp64": (1, "f64", "FP64 storage", "fp64"),
+              "fp32-massexact": (2, "f32", "mass-exact FP32 deviation storage", "fp32_massexact")}
+
+
+def pmc_file(tag):
+    return os.path.join(ROOT, "profiles", "pmc_step_8192x512_%s.json" % tag)
 KERNEL_SRC = os.path.join(ROOT, "paper_1803_01756_amd", "csrc", "lbm_kernels.hip")
 
 
@@ -62,11 +69,13 @@ def kernel_sha():
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def counter_traffic():
-    """HBM bytes per launch from the committed counter summary, or None."""
-    if not os.path.exists(PMC_FILE):
+def counter_traffic(tag="fp32"):
+    """HBM bytes per launch from the committed counter summary of this
+    storage, or None (no summary, or one taken from other kernel source)."""
+    path = pmc_file(tag)
+    if not os.path.exists(path):
         return None
-    with open(PMC_FILE) as fh:
+    with open(path) as fh:
         d = json.load(fh)
     if d.get("source_sha256") != kernel_sha():
         return None
@@ -405,7 +414,10 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10000)
     ap.add_argument("--serve-requests", type=int, default=110)
     ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp32",
+                    help="storage of the headline 8192x512 run (default fp32)")
     args = ap.parse_args()
+    prec, dtype, storage, tag = PRECISIONS[args.precision]
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: the step runs on a single MI355X and this "
@@ -422,17 +434,17 @@ def main():
     log("bandwidth probe (plain copy, 1 GiB)")
     probe_gbs, _ = lbm.lbm_bandwidth_probe(1 << 30, 20)
 
-    p = configs.large_channel(lbm.LBM_FP32_DEV)
+    p = configs.large_channel(prec)
     rho0 = configs.initial_density(p, seed=1)
     n = fluid_nodes(p)
-    log("8192x512 fp32: tune + %d warmup + %d timed steps" % (args.warmup, args.steps))
+    log("8192x512 %s: tune + %d warmup + %d timed steps" % (args.precision, args.warmup, args.steps))
     ms, wall_ms, seg, waves, red = run_config(p, rho0, args.steps, args.warmup,
                                               tune=not args.no_tune, seg_rows=args.seg_rows)
     ms_step = ms / args.steps
     mlups = n * args.steps / (ms * 1e-3) / 1e6
-    achieved = BYTES_PER_LUP[0] * n / (ms_step * 1e-3) / 1e9
-    traffic = counter_traffic()
-    log("fp32 %.4f ms/step  %.0f MLUPS  %.0f GB/s algorithmic" % (ms_step, mlups, achieved))
+    achieved = BYTES_PER_LUP[prec] * n / (ms_step * 1e-3) / 1e9
+    traffic = counter_traffic(tag)
+    log("%s %.4f ms/step  %.0f MLUPS  %.0f GB/s algorithmic" % (args.precision, ms_step, mlups, achieved))
 
     extra = {}
     if not args.no_extra:
@@ -484,15 +496,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": "plate channel 8192x512, FP32 deviation storage, Tw=0.78Tc, "
-                               "75 deg wall, drive 2e-6 / 4000 steps, seeded vapour noise",
+        "config": {"workload": "plate channel 8192x512, %s, Tw=0.78Tc, "
+                               "75 deg wall, drive 2e-6 / 4000 steps, seeded vapour noise" % storage,
                    "Nx": p.Nx, "Ny": p.Ny, "fluid_nodes": n, "seg_rows": seg, "waves": waves},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "bytes_per_lup": BYTES_PER_LUP[0],
+                     "bytes_per_lup": BYTES_PER_LUP[prec],
                      "copy_probe_gbs": round(probe_gbs, 1),
                      "frac_of_copy_probe": round(achieved / probe_gbs, 4),
                      # HBM bytes the counters saw per launch, over the same time
