@@ -43,7 +43,10 @@ PRECISIONS = {"fp32": (0, "f32", "FP32 deviation storage", "fp32"),
 
 def pmc_file(tag):
     return os.path.join(ROOT, "profiles", "pmc_step_8192x512_%s.json" % tag)
-KERNEL_SRC = os.path.join(ROOT, "paper_1803_01756_amd", "csrc", "lbm_kernels.hip")
+# the sources that decide what a step launch reads and writes: the kernels and
+# the device layout (plane stride, pitch, buffer offsets)
+TRAFFIC_SRCS = [os.path.join(ROOT, "paper_1803_01756_amd", "csrc", f)
+                for f in ("lbm_kernels.hip", "lbm_runtime.cpp", "lbm_host.h")]
 
 
 def log(msg):
@@ -65,8 +68,13 @@ def host_info():
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    """sha256 over the kernel and layout sources, in order; a counter summary
+    taken from other sources is not used."""
+    h = hashlib.sha256()
+    for path in TRAFFIC_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def counter_traffic(tag="fp32"):
@@ -449,13 +457,13 @@ def main():
     extra = {}
     if not args.no_extra:
         k = max(200, args.steps // 4)
-        for name, prec in (("fp64", lbm.LBM_FP64), ("fp32_massexact", lbm.LBM_FP32_DEV_MASSEXACT)):
-            q = configs.large_channel(prec)
+        for name, prec2 in (("fp64", lbm.LBM_FP64), ("fp32_massexact", lbm.LBM_FP32_DEV_MASSEXACT)):
+            q = configs.large_channel(prec2)
             log("8192x512 %s: %d steps" % (name, k))
             m2, _, s2, _, _ = run_config(q, rho0, k, 20, tune=not args.no_tune)
             extra[name] = dict(mlups=round(n * k / (m2 * 1e-3) / 1e6, 1),
                                ms_per_step=round(m2 / k, 5), seg_rows=s2,
-                               hbm_gbs_algorithmic=round(BYTES_PER_LUP[prec] * n / (m2 / k * 1e-3) / 1e9, 1))
+                               hbm_gbs_algorithmic=round(BYTES_PER_LUP[prec2] * n / (m2 / k * 1e-3) / 1e9, 1))
         q = configs.single_gpu_channel(90.0, lbm.LBM_FP32_DEV)
         r2 = configs.initial_density(q, seed=1)
         log("2048x256 fp32 (cache-resident): %d steps" % (4 * k))

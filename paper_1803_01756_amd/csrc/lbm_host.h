@@ -12,9 +12,18 @@ namespace lbmhost {
 constexpr int kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Elements added to the population plane stride beyond pitch x rows (a
+// multiple of 64, so rows keep their 256-byte alignment).  When pitch x rows
+// is a multiple of a large power of two (8192 x 510 FP32 values are
+// 255 x 64 KiB) the nine planes of one row start at addresses that agree in
+// all their low bits and their loads and stores pile onto the same HBM
+// channels; skewing each plane by 3.25 KiB (FP32) spreads them.
+constexpr size_t kPlaneSkew = 832;
+
 // Device memory layout of one channel: two population buffers
-// [9][rows][pitch], optional mass-exact low planes, two temperature planes,
-// then the moment arrays and reduction scratch.
+// [9][rows][pitch] with a plane stride of pitch x rows + kPlaneSkew,
+// optional mass-exact low planes, two temperature planes, then the moment
+// arrays and reduction scratch.
 struct Layout {
     int pitch, rows;
     size_t plane, esz;

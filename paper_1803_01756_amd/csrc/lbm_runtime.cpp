@@ -231,7 +231,7 @@ bool make_layout(const lbm_params& p, Layout* L) {
     const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
     L->pitch = (p.Nx + 63) / 64 * 64;
     L->rows = per ? p.Ny : p.Ny - 2;
-    L->plane = (size_t)L->pitch * L->rows;
+    L->plane = (size_t)L->pitch * L->rows + kPlaneSkew;
     L->esz = p.precision == LBM_FP64 ? 8 : 4;
 
     const size_t cells = (size_t)p.Nx * p.Ny;

@@ -229,9 +229,10 @@ def test_nonfinite_state_is_reported():
     p = configs.oracle_size_channel()
     s = lbm.Sim(p, configs.initial_density(p, seed=9))
     blob = bytearray(s.save())
-    # overwrite one stored population (bytes of the f plane) with a NaN
-    hdr = len(blob) - (9 + 1) * 128 * 30 * 4
-    blob[hdr + 4 * 1000: hdr + 4 * 1001] = np.array([np.nan], dtype=np.float32).tobytes()
+    # overwrite 8 KiB in the middle of the stored populations with 0xFF bytes
+    # (a NaN at any alignment; wider than the unused tail of any plane)
+    mid = len(blob) // 2
+    blob[mid - 8192: mid] = b"\xff" * 8192
     s.load(bytes(blob))
     s.step(3)
     with pytest.raises(lbm.LBMError) as ei:
