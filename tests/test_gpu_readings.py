@@ -1,0 +1,137 @@
+"""GPU parity of the parts of the step that the default parameter set leaves
+idle, element by element against the FP64 oracle, in all three storages.
+
+* Eq. 5 with tau_g != tau_l on a liquid layer whose densities reach below
+  rho_g and above rho_l, so both clamps of the interpolation fraction act
+  (checked on the oracle's fields at the start and at the end of the run).
+* Eq. 3 rates other than the defaults (s_rho, s_e = s_zeta, s_j, s_q) and an
+  Eq. 8 theta other than 0.104, on the same interface field, where the
+  theta term |F_m|^2 / psi^2 is large.
+* The edge grids of the FP64 edge test (strips narrower than a wave, widths
+  around the 54-column strip boundary, one or two fluid rows) in FP32 and
+  mass-exact storage, whose row loads run one iteration ahead.
+* lbm_reduce against the sums of the oracle's own fields.
+
+Tolerances.  FP64: 1e-11 relative on rho and T, 1e-9 normwise on u (the
+summation order differs from the oracle's).  FP32 deviation storage: the
+1e-5 bar of the headline, relative on rho and T, normwise on u.  A liquid
+layer stores deviations of ~6 from rho_ref = rho_v, so FP32 rounding there is
+~5e-7 absolute per step; the layer cases run 50 steps in FP32 (150 in FP64),
+as the phase-dependent-property test does.
+"""
+import numpy as np
+import pytest
+
+from helpers import field_errors, fluid_mask, to_oracle
+from paper_1803_01756_amd import configs, inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT]
+
+
+def _case(name):
+    print("\n[case] %s" % name, flush=True)
+
+
+def _gpu(p, rho0, steps):
+    s = lbm.Sim(p, rho0)
+    s.step(steps)
+    out = s.moments()
+    s.close()
+    return out
+
+
+def _oracle(orc, p, rho0, steps):
+    o = orc.Sim(to_oracle(orc, p), rho0)
+    o.step(steps)
+    return o.moments()
+
+
+def _tol(precision):
+    return (1e-11, 1e-9, 1e-11) if precision == lbm.LBM_FP64 else (1e-5, 1e-5, 1e-5)
+
+
+def _layer(Nx, Ny, lo, hi, seed):
+    """A liquid layer on the lower plate: tanh profile (centre y = 7.5,
+    width 2) from hi at the plate to lo above it, with 1 % seeded noise."""
+    y = np.arange(Ny)[:, None] * np.ones((1, Nx))
+    layer = 0.5 * (1 - np.tanh((y - 7.5) / 2.0))
+    noise = inputs.density_field(Nx, Ny, 1.0, 0.01, seed)
+    return (lo + (hi - lo) * layer) * noise
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_eq5_interpolated_tau_both_clamps(orc, precision):
+    _case("Eq. 5 tau_g=0.7 tau_l=1.4, 80x32 layer, precision=%d" % precision)
+    p = configs.channel_params(80, 32, 90.0, 0.78, 2e-5, 200.0, precision, 0,
+                               tau_g=0.7, tau_l=1.4)
+    rho0 = _layer(80, 32, 0.9 * p.rho_g, 1.03 * p.rho_l, 4)
+    m = fluid_mask(80, 32)
+    assert (rho0[m] < p.rho_g).sum() > 100 and (rho0[m] > p.rho_l).sum() > 100
+    n = 150 if precision == lbm.LBM_FP64 else 50
+    r = _oracle(orc, p, rho0, n)
+    # both clamps still act at the last compared step
+    assert (r[0][m] < p.rho_g).sum() > 100 and (r[0][m] > p.rho_l).sum() > 100
+    e = field_errors(_gpu(p, rho0, n), r, m)
+    print(e, flush=True)
+    tol = _tol(precision)
+    assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_eq3_rates_and_theta_off_default(orc, precision):
+    _case("Eq. 3 rates (0.6, 1.25, 1.25, 1.4, 1.6), theta 0.05, 80x32 layer, precision=%d"
+          % precision)
+    p = configs.channel_params(80, 32, 120.0, 0.80, 2e-5, 200.0, precision, 0,
+                               s_rho=0.6, s_e=1.25, s_zeta=1.25, s_j=1.4, s_q=1.6,
+                               theta=0.05, tau_g=0.9, tau_l=1.1)
+    rho0 = _layer(80, 32, p.rho_g, p.rho_l, 9)
+    n = 150 if precision == lbm.LBM_FP64 else 50
+    e = field_errors(_gpu(p, rho0, n), _oracle(orc, p, rho0, n), fluid_mask(80, 32))
+    print(e, flush=True)
+    tol = _tol(precision)
+    assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
+
+
+@pytest.mark.parametrize("Nx,Ny", [(3, 4), (20, 5), (54, 6), (55, 7), (65, 9), (130, 12),
+                                   (109, 40)])
+@pytest.mark.parametrize("precision", [lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
+def test_edge_grids_fp32(orc, precision, Nx, Ny):
+    _case("edge grid %dx%d precision=%d" % (Nx, Ny, precision))
+    p = configs.channel_params(Nx, Ny, 120.0, 0.8, 1e-5, 50.0, precision)
+    rho0 = configs.initial_density(p, seed=Nx * 100 + Ny)
+    e = field_errors(_gpu(p, rho0, 30), _oracle(orc, p, rho0, 30), fluid_mask(Nx, Ny))
+    print(e, flush=True)
+    assert e["rho"] < 1e-5 and e["u"] < 1e-5 and e["T"] < 1e-5
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_reduce_against_oracle_sums(orc, precision):
+    """out[0..3] of lbm_reduce against sum rho, sum rho u and sum rho C_v T of
+    the oracle's fields.  The bound follows from the per-node bars: with
+    relative errors e_rho on rho and normwise e_u on u,
+      |sum rho - sum rho'| <= e_rho sum rho,
+      |sum rho u - sum rho' u'| <= e_u max|u'| sum rho + e_rho sum rho |u'|,
+      |sum rho T - sum rho' T'| <= (e_rho + e_T + e_rho e_T) sum rho T."""
+    _case("lbm_reduce vs oracle sums 96x28 precision=%d" % precision)
+    p = configs.channel_params(96, 28, 60.0, 0.78, 2e-4, 300.0, precision)
+    rho0 = configs.initial_density(p, seed=12)
+    s = lbm.Sim(p, rho0)
+    s.step(120)
+    red = s.reduce()
+    s.close()
+    rho, ux, uy, T, _, _ = _oracle(orc, p, rho0, 120)
+    m = fluid_mask(96, 28)
+    e_rho, e_u, e_T = _tol(precision)
+    M = rho[m].sum()
+    umax = np.hypot(ux, uy)[m].max()
+    bound_j = e_u * umax * M + e_rho * (rho * np.hypot(ux, uy))[m].sum()
+    E = (rho * p.C_v * T)[m].sum()
+    print(dict(mass=(red[0] - M) / M, jx=(red[1] - (rho * ux)[m].sum()) / bound_j,
+               jy=(red[2] - (rho * uy)[m].sum()) / bound_j, E=(red[3] - E) / E), flush=True)
+    assert abs(red[0] - M) <= e_rho * M
+    assert abs(red[1] - (rho * ux)[m].sum()) <= bound_j
+    assert abs(red[2] - (rho * uy)[m].sum()) <= bound_j
+    assert abs(red[3] - E) <= (e_rho + e_T + e_rho * e_T) * E
+    assert red[4] == 0
