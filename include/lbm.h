@@ -23,9 +23,14 @@
  *   - Host arrays are caller-owned and indexed [y*Nx + x], y = 0..Ny-1.
  *   - Device memory and streams are plain pointers (hipStream_t is passed as
  *     void*).  A NULL stream means the library creates its own.
- *   - lbm_step only enqueues work.  Device faults and a non-finite state
- *     surface on the next synchronising call (lbm_moments, lbm_reduce,
- *     lbm_synchronize) as LBM_EDEVICE / LBM_EUNSTABLE.
+ *   - lbm_step only enqueues work.  Device faults surface on the next
+ *     synchronising call as LBM_EDEVICE.  A non-finite state surfaces as
+ *     LBM_EUNSTABLE: every step checks the rho and T it reads (the state at
+ *     its own time level) on every fluid node and counts the non-finite
+ *     ones on the device; lbm_synchronize reports any such count, and
+ *     lbm_moments and lbm_reduce also check the current time level (the
+ *     state the last step wrote).  The count is kept until lbm_load
+ *     replaces the state (lbm_health reads it).
  *   - A simulation must not be used from two threads at once.
  */
 #ifndef PAPER_1803_01756_LBM_H
@@ -179,6 +184,10 @@ lbm_status lbm_eos_pressure(const lbm_params* p, double rho, double T, double* P
  * LBM_EINVAL if T is not below T_c or no coexistence is found. */
 lbm_status lbm_eos_latent_heat(const lbm_params* p, double T, double* h_fg);
 
+/* Jacob number of Eq. 20, Ja = C_v (T_sat - T_w) / h_fg(T_sat), with h_fg
+ * from lbm_eos_latent_heat.  Host FP64; LBM_EINVAL as lbm_eos_latent_heat. */
+lbm_status lbm_eos_jacob(const lbm_params* p, double T_sat, double T_w, double* Ja);
+
 /* Device bytes a simulation with these parameters needs (two population
  * buffers, two temperature buffers, moment scratch), for callers that
  * provide the memory themselves.  0 if the parameters are invalid. */
@@ -196,8 +205,11 @@ size_t lbm_workspace_bytes(const lbm_params* p);
  *   stream     hipStream_t all work is ordered on, or NULL for a private stream
  *   out        receives the handle
  * LBM_EINVAL: Nx < 3, Ny < 4 (Ny < 3 with LBM_PERIODIC_Y), G = 0, a relaxation
- * rate outside (0, 2), tau <= 1/2, s_e != s_zeta, b*rho >= 1 at the initial
- * state, or a workspace that is too small.  LBM_ENOMEM, LBM_EDEVICE. */
+ * rate outside (0, 2), tau <= 1/2, s_e != s_zeta, an initial density that is
+ * not positive, reaches the EOS packing limit (b rho >= 1; >= 4 for
+ * LBM_EOS_CS) or makes the Eq. 10 argument 2 (P_EOS - rho/3) / G negative at
+ * the node's initial temperature (no real psi: P - rho/3 > 0 for G < 0), or
+ * a workspace that is too small.  LBM_ENOMEM, LBM_EDEVICE. */
 lbm_status lbm_create(const lbm_params* p, const double* rho0, void* workspace,
                       size_t ws_bytes, void* stream, lbm_sim** out);
 
@@ -206,17 +218,33 @@ lbm_status lbm_step(lbm_sim* sim, int64_t n);
 
 /* Synchronise and copy rho, u (the half-force velocity of Eq. 13) and T at
  * the current time level into caller-owned host arrays of Nx*Ny doubles
- * (any may be NULL).  Solid rows give rho = 0, u = 0, T = T_w. */
+ * (any may be NULL).  Solid rows give rho = 0, u = 0, T = T_w.  The arrays
+ * are filled also when the call returns LBM_EUNSTABLE (some step read a
+ * non-finite rho or T, or the current level holds one). */
 lbm_status lbm_moments(lbm_sim* sim, double* rho, double* ux, double* uy, double* T);
 
 /* Synchronise and reduce in FP64 with a fixed summation order:
  * out[0] = sum rho, out[1] = sum rho u_x, out[2] = sum rho u_y,
  * out[3] = sum rho C_v T, out[4] = number of non-finite nodes.
- * Returns LBM_EUNSTABLE when out[4] > 0. */
+ * Returns LBM_EUNSTABLE when out[4] > 0 or some step read a non-finite
+ * state. */
 lbm_status lbm_reduce(lbm_sim* sim, double out[5]);
 
-/* Wait for all enqueued work; LBM_EDEVICE on a device error. */
+/* Wait for all enqueued work.  LBM_EDEVICE on a device error,
+ * LBM_EUNSTABLE when some completed step read a non-finite rho or T. */
 lbm_status lbm_synchronize(lbm_sim* sim);
+
+/* Synchronise and read the health counters the steps keep on the device
+ * (never reset by a step; lbm_load restarts them):
+ *   nonfinite   fluid-node readings of a non-finite rho or T, summed over
+ *               the steps taken (each step reads the state of its own time
+ *               level once per node),
+ *   psi_clamps  fluid-node evaluations of Eq. 10 whose argument
+ *               2 (P_EOS - rho/3) / G was not positive, so that psi was
+ *               clamped to 0, summed over the steps taken.
+ * Either pointer may be NULL.  Returns LBM_OK with the counts (LBM_EDEVICE
+ * on a device error); the counts do not change the status. */
+lbm_status lbm_health(lbm_sim* sim, int64_t* nonfinite, int64_t* psi_clamps);
 
 /* Destroy; NULL is accepted.  Frees library-owned memory and stream. */
 lbm_status lbm_destroy(lbm_sim* sim);
@@ -262,7 +290,14 @@ lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_trial, double* best_ms);
  * Admission is by device footprint against the pool's byte cap; start-up and
  * read-out run on a second stream, so slots can be admitted and results read
  * while a chunk runs (continuous batching).  A slot's results are bitwise
- * those of the same channel run alone with lbm_create/lbm_step. */
+ * those of the same channel run alone with lbm_create/lbm_step.
+ *
+ * A slot whose steps read a non-finite rho or T is retired: once the
+ * counters copied at the end of a chunk show it (at the latest two chunks
+ * after it happened) it takes no further steps, lbm_pool_poll reports it
+ * as finished, and lbm_pool_moments returns LBM_EUNSTABLE for it.  The
+ * other slots are not affected: a slot's step reads and writes only its
+ * own memory. */
 
 /* Device bytes one slot with these parameters holds (two population
  * buffers, two temperature planes); 0 if the parameters are invalid. */
@@ -275,8 +310,9 @@ lbm_status lbm_pool_create(size_t cap_bytes, void* stream, lbm_pool** out);
 /* Admit a channel that is to run nsteps steps.  rho0: host Nx*Ny initial
  * densities or NULL (uniform rho_v).  *slot receives its id.
  * LBM_ENOMEM when its footprint does not fit under the cap (the caller keeps
- * the request queued), LBM_EINVAL for invalid parameters or a precision
- * other than LBM_FP32_DEV. */
+ * the request queued), LBM_EINVAL for invalid parameters or initial
+ * densities (the checks of lbm_create) or a precision other than
+ * LBM_FP32_DEV. */
 lbm_status lbm_pool_admit(lbm_pool* pool, const lbm_params* p, const double* rho0,
                           int64_t nsteps, int32_t* slot);
 
@@ -288,14 +324,22 @@ lbm_status lbm_pool_run(lbm_pool* pool, int32_t chunk_steps);
  * back-pressure for a serving loop that enqueues ahead of the device). */
 lbm_status lbm_pool_wait(lbm_pool* pool, int32_t max_pending);
 
-/* Non-blocking: ids of slots that have finished all their steps and were
- * not reported before (at most max of them) into done[], count in *ndone. */
+/* Non-blocking: ids of slots that have finished all their steps, or were
+ * retired with a non-finite state, and were not reported before (at most
+ * max of them) into done[], count in *ndone. */
 lbm_status lbm_pool_poll(lbm_pool* pool, int32_t* done, int32_t max, int32_t* ndone);
 
 /* rho, u, T of a slot at its current time level into host arrays of Nx*Ny
- * doubles (any may be NULL), as lbm_moments.  Waits for that slot only. */
+ * doubles (any may be NULL), as lbm_moments.  Waits for that slot only.
+ * LBM_EUNSTABLE (arrays filled) when the slot's steps read a non-finite
+ * state or its current level holds one. */
 lbm_status lbm_pool_moments(lbm_pool* pool, int32_t slot, double* rho, double* ux, double* uy,
                             double* T);
+
+/* The health counters of a slot (as lbm_health), after the work enqueued
+ * for it so far.  Waits for that slot only. */
+lbm_status lbm_pool_slot_health(lbm_pool* pool, int32_t slot, int64_t* nonfinite,
+                                int64_t* psi_clamps);
 
 /* Retire a slot; its footprint returns to the cap and its id may be reused. */
 lbm_status lbm_pool_release(lbm_pool* pool, int32_t slot);

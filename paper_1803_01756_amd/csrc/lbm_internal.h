@@ -79,6 +79,10 @@ struct Bufs {
     unsigned fin, fout;       // population buffers: 9 planes of S
     unsigned lo_in, lo_out;   // mass-exact low parts of the rest population (float)
     unsigned Tin, Tout;       // temperature planes (Tout unused when T is frozen)
+    // health counters, added to by every step: [0] owned nodes whose state
+    // at the step's time level holds a non-finite rho or T, [1] owned nodes
+    // whose Eq. 10 argument was clamped (psi = 0)
+    unsigned long long* stat;
 };
 
 constexpr int kWavesPerBlock = 4;
@@ -105,6 +109,7 @@ struct Slot {
     int cur_f, cur_T;
     int steps_left;
     int unit_begin;  // first unit of this slot in the batch numbering
+    unsigned long long* stat;  // the slot's health counters (see Bufs::stat)
 };
 
 // Step i of a chunk over every slot of the table (slots sorted by
@@ -116,13 +121,15 @@ hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, 
                                hipStream_t s);
 
 // rho, u (half force) and T at the current time level into device arrays of
-// Nx*Ny doubles; scratch holds 3*Nx*Ny doubles.
+// Nx*Ny doubles; work holds 3*Nx*Ny doubles; *n_bad is incremented for
+// every fluid node whose rho or T is not finite.
 hipError_t launch_moments_f32(const Grid& g, const Phys& k, const float* f, const float* f0lo,
-                              const float* T, double* scratch, double* rho, double* ux,
-                              double* uy, double* Tout, int64_t n, hipStream_t s);
+                              const float* T, double* work, double* rho, double* ux,
+                              double* uy, double* Tout, int64_t n, unsigned long long* n_bad,
+                              hipStream_t s);
 hipError_t launch_moments_f64(const Grid& g, const Phys& k, const double* f, const double* T,
-                              double* scratch, double* rho, double* ux, double* uy,
-                              double* Tout, int64_t n, hipStream_t s);
+                              double* work, double* rho, double* ux, double* uy,
+                              double* Tout, int64_t n, unsigned long long* n_bad, hipStream_t s);
 
 // Rest-equilibrium start from a device density field rho0 (Nx*Ny doubles).
 hipError_t launch_init_f32(const Grid& g, const Phys& k, const double* rho0, float* f,

@@ -270,14 +270,17 @@ __device__ __forceinline__ double sqrt_d(double x) {
 //   P = rho R T (1 + e + e^2 - e^3) / (1 - e)^3 - a rho^2.
 // kExt: the build that also serves the optional features (here the
 // Carnahan-Starling EOS); the plain build leaves their code out.
+// clamped: set when the argument is not positive (psi is then 0), the event
+// the step counts per owned node.
 template <bool kF32, bool kExt = true>
-__device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k) {
+__device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k, bool& clamped) {
     constexpr int kNewton = kF32 ? 1 : 2;
     if (kExt && (k.flags & kEosCS)) {
         const double e = 0.25 * k.b * rho, o = 1.0 - e;
         const double Z = (1.0 + e * (1.0 + e * (1.0 - e))) * rcp_d<kNewton>(o * o * o);
         const double P = rho * (k.R * T * Z - k.a * rho);
         const double arg = 2.0 * (P - rho * (1.0 / 3.0)) * k.inv_G;
+        clamped = !(arg > 0.0);
         return arg > 0.0 ? sqrt_d<kNewton>(arg) : 0.0;
     }
     const double st = kF32 ? (double)__builtin_amdgcn_sqrtf((float)(T * k.inv_Tc))
@@ -289,6 +292,7 @@ __device__ __forceinline__ double psi_eos(double rho, double T, const Phys& k) {
     const double num = rho * (k.R * T * D - k.a * (s * s) * rho * omb);
     const double P = num * rcp_d<kNewton>(omb * D);
     const double arg = 2.0 * (P - rho * (1.0 / 3.0)) * k.inv_G;
+    clamped = !(arg > 0.0);
     return arg > 0.0 ? sqrt_d<kNewton>(arg) : 0.0;
 }
 
@@ -556,6 +560,22 @@ __device__ __forceinline__ int unit_of_block(int nblocks_pad) {
     return ((b & 7) * per + (b >> 3));
 }
 
+// Add a wave's health word (see step_unit) to the counters: stat[0] gains
+// the number of lanes (node columns of the segment) that read a non-finite
+// value, stat[1] the clamped Eq. 10 arguments.  Called by every lane of the
+// wave; the sums and the atomics run only when some lane counted anything.
+__device__ __forceinline__ void flush_health(unsigned long long* stat, unsigned health) {
+    if (__builtin_amdgcn_ballot_w64(health != 0u) == 0ull) return;
+    const unsigned long long bad = __builtin_amdgcn_ballot_w64((health >> 31) != 0u);
+    unsigned clamp = health & 0x7fffffffu;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) clamp += __shfl_xor(clamp, off, 64);
+    if ((threadIdx.x & (kLanes - 1)) == 0) {
+        if (bad) atomicAdd(&stat[0], (unsigned long long)__builtin_popcountll(bad));
+        if (clamp) atomicAdd(&stat[1], (unsigned long long)clamp);
+    }
+}
+
 // One wave's share of a step: the strip and row segment of `unit`.  kExt
 // compiles in the optional features (held and reservoir frames, the
 // Carnahan-Starling EOS, open ends and plate temperature ramps,
@@ -676,6 +696,11 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     Tri<R> t1a, t1b, t1c, t2a, t2b, t2c, t3a, t3b, t3c;
     R acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0;  // sum of the h's, rows k-2 .. k-5
     double drdCur = 0.0, drdPrv = 0.0;         // mass-exact: FP64 deviation density
+    // health of the owned nodes (the state at level n), in one register:
+    // bits 0-30 count the Eq. 10 arguments clamped to psi = 0 (a lane owns
+    // fewer than 2^20 rows), bit 31 is set once the lane has read a
+    // non-finite rho or T
+    unsigned health = 0;
 
 #pragma unroll
     for (int q = 0; q < 9; ++q) dPrv[q] = dCur[q] = 0;
@@ -783,7 +808,8 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             rhoCur = (R)rho_d;
             dTA = (R)rawT;
             const double Td = k.T_ref + (double)dTA;
-            psiA = trix(psi_eos<sizeof(S) == 4, kExt>(rho_d, Td, k));
+            bool clamped;
+            psiA = trix(psi_eos<sizeof(S) == 4, kExt>(rho_d, Td, k, clamped));
         } else {
             drCur = 0;
             drdCur = 0.0;
@@ -851,6 +877,11 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                         dn[q] = (R)((q == 0 ? 4.0 / 9 : (q < 5 ? 1.0 / 9 : 1.0 / 36)) * dr);
                 }
                 if (own_lane) {
+                    // health of the owned node (state at level n): psi is 0
+                    // exactly when Eq. 10 was clamped (a NaN argument too)
+                    health += psi1.c == 0.0 ? 1u : 0u;
+                    if (!(__builtin_isfinite(rho) && __builtin_isfinite(tn1.c)))
+                        health |= 0x80000000u;
                     const unsigned so = B.fout + (unsigned)rB.sr * rowb;
                     if (kMX) {
                         // rest population takes whatever keeps sum_i d_i equal to
@@ -1005,6 +1036,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         step_row(kr + 4);
         step_row(kr + 5);
     }
+    flush_health(B.stat, health);
 }
 
 // wave index inside the block, as a wave-uniform value
@@ -1064,6 +1096,7 @@ void step_batched_kernel(
     B.fin = sl.off_f[a];
     B.fout = sl.off_f[a ^ 1];
     B.lo_in = B.lo_out = 0;
+    B.stat = sl.stat;
     if (sl.k.flags & kFreezeT) {
         B.Tin = B.Tout = sl.off_T[sl.cur_T];
     } else {
@@ -1083,31 +1116,33 @@ __device__ __forceinline__ bool reservoir_node(const Grid& g, int cx, int y) {
            (cx == 0 || cx == g.Nx - 1 || (g.periodic_y && (y == 0 || y == g.Ny - 1)));
 }
 
-// pass 1: rho, psi, j (and T) per node into scratch; pass 2: forces and u.
+// The read-out's arithmetic per node, shared by the two-pass read-out and
+// the one-pass reduction, so that both see bitwise the same node values.
+struct NodeState {
+    double rho, psi, jx, jy, T;  // rho = 0 and j = 0 on plate rows
+    bool fluid;
+};
+
+// rho, psi, j and T of node (cx, y) (y counts the plate rows) at time level
+// n_t from the stored post-collision state.
 template <class S, bool kMX>
-__global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __restrict__ f,
-                                                     const float* __restrict__ f0lo,
-                                                     const S* __restrict__ T,
-                                                     double* __restrict__ scratch,
-                                                     double* __restrict__ rho_out,
-                                                     double* __restrict__ T_out, long long n_t) {
-    const int n = g.Nx * g.Ny;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int y = i / g.Nx, cx = i - y * g.Nx;
-    double* psi = scratch;
-    double* jx = scratch + n;
-    double* jy = scratch + 2 * n;
+__device__ __forceinline__ NodeState node_state(const Grid& g, const Phys& k,
+                                                const S* __restrict__ f,
+                                                const float* __restrict__ f0lo,
+                                                const S* __restrict__ T, int cx, int y,
+                                                long long n_t) {
+    NodeState o;
     const RowK r = row_info(y, g);
+    o.fluid = r.fluid;
     if (!r.fluid) {
-        psi[i] = k.psi_wall_eff;
-        jx[i] = jy[i] = 0.0;
-        rho_out[i] = 0.0;
-        T_out[i] = k.T_ref + (k.wall_ramp ? k.dT_wall + (k.dT_w_end - k.dT_wall) * (double)cx /
-                                                              (double)(g.Nx - 1)
-                              : ((k.flags & kTopMixed) && y == 0) ? k.dT_w_bot
-                                                                  : k.dT_wall);
-        return;
+        o.psi = k.psi_wall_eff;
+        o.jx = o.jy = 0.0;
+        o.rho = 0.0;
+        o.T = k.T_ref + (k.wall_ramp ? k.dT_wall + (k.dT_w_end - k.dT_wall) * (double)cx /
+                                                       (double)(g.Nx - 1)
+                         : ((k.flags & kTopMixed) && y == 0) ? k.dT_w_bot
+                                                             : k.dT_wall);
+        return o;
     }
     const unsigned x = (unsigned)cx;
     const unsigned xm = (unsigned)(cx == 0 ? g.Nx - 1 : cx - 1);
@@ -1130,20 +1165,71 @@ __global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __
     if (kMX) dr += (double)f0lo[(unsigned)r.sr * (unsigned)g.pitch + x];
     const bool res = reservoir_node(g, cx, y);
     if (res) dr = k.rho_frame - k.rho_ref;
-    const double rho = k.rho_ref + dr;
-    const double Td = k.T_ref + (double)T[(unsigned)r.sr * (unsigned)g.pitch + x];
-    rho_out[i] = rho;
-    T_out[i] = Td;
-    psi[i] = psi_eos<sizeof(S) == 4>(rho, Td, k);
-    jx[i] = ((double)d[1] - (double)d[3]) + ((double)d[5] - (double)d[6]) +
-            ((double)d[8] - (double)d[7]);
-    jy[i] = ((double)d[2] - (double)d[4]) + ((double)d[5] + (double)d[6]) -
-            ((double)d[7] + (double)d[8]);
-    if (res) jx[i] = jy[i] = 0.0;
+    o.rho = k.rho_ref + dr;
+    o.T = k.T_ref + (double)T[(unsigned)r.sr * (unsigned)g.pitch + x];
+    bool clamped;
+    o.psi = psi_eos<sizeof(S) == 4>(o.rho, o.T, k, clamped);
+    o.jx = ((double)d[1] - (double)d[3]) + ((double)d[5] - (double)d[6]) +
+           ((double)d[8] - (double)d[7]);
+    o.jy = ((double)d[2] - (double)d[4]) + ((double)d[5] + (double)d[6]) -
+           ((double)d[7] + (double)d[8]);
+    if (res) o.jx = o.jy = 0.0;
+    return o;
+}
+
+// u of a fluid node (Eq. 13) from its rho and j and the psi of the rows
+// below (pS), at (pC) and above (pN) it, each as centre / x-sum / x-difference.
+__device__ __forceinline__ void node_velocity(const Grid& g, const Phys& k, int cx, int y,
+                                              const Tri<double>& pS, const Tri<double>& pC,
+                                              const Tri<double>& pN, double rho, double jx,
+                                              double jy, long long n_t, double& ux,
+                                              double& uy) {
+    const RowK r = row_info(y, g);
+    double Fx = 0.0, Fy = 0.0;
+    if (!(k.flags & kSinglePhase))
+        pair_force(pS, pC, pN, k.negG, Fx, Fy);
+    else
+        Fy = wall_adhesion_y(r, pC.c, k);
+    Fx += rho * drive_at(k, n_t) + (rho - k.rho_v) * k.g_x;
+    Fy += (rho - k.rho_v) * k.g_y;
+    ux = (jx + 0.5 * Fx) / rho;
+    uy = (jy + 0.5 * Fy) / rho;
+    if (reservoir_node(g, cx, y)) ux = uy = 0.0;
+}
+
+// the x-neighbours the read-out uses: periodic, or past an open end the end
+// column itself
+__device__ __forceinline__ int read_xm(const Grid& g, int cx) {
+    return cx == 0 ? (g.open_x ? 0 : g.Nx - 1) : cx - 1;
+}
+__device__ __forceinline__ int read_xp(const Grid& g, int cx) {
+    return cx == g.Nx - 1 ? (g.open_x ? cx : 0) : cx + 1;
+}
+
+// pass 1: rho, psi, j (and T) per node into scratch; pass 2: forces and u.
+template <class S, bool kMX>
+__global__ __launch_bounds__(256) void moments_pass1(Grid g, Phys k, const S* __restrict__ f,
+                                                     const float* __restrict__ f0lo,
+                                                     const S* __restrict__ T,
+                                                     double* __restrict__ work,
+                                                     double* __restrict__ rho_out,
+                                                     double* __restrict__ T_out, long long n_t,
+                                                     unsigned long long* __restrict__ n_bad) {
+    const int n = g.Nx * g.Ny;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int y = i / g.Nx, cx = i - y * g.Nx;
+    const NodeState o = node_state<S, kMX>(g, k, f, f0lo, T, cx, y, n_t);
+    work[i] = o.psi;
+    work[n + i] = o.jx;
+    work[2 * n + i] = o.jy;
+    rho_out[i] = o.rho;
+    T_out[i] = o.T;
+    if (o.fluid && !(__builtin_isfinite(o.rho) && __builtin_isfinite(o.T))) atomicAdd(n_bad, 1ull);
 }
 
 __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
-                                                     const double* __restrict__ scratch,
+                                                     const double* __restrict__ work,
                                                      const double* __restrict__ rho_in,
                                                      double* __restrict__ ux_out,
                                                      double* __restrict__ uy_out, long long n_t) {
@@ -1156,12 +1242,10 @@ __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
         ux_out[i] = uy_out[i] = 0.0;
         return;
     }
-    const double* psi = scratch;
-    const double* jx = scratch + n;
-    const double* jy = scratch + 2 * n;
-    // periodic in x, or the end column itself past an open end
-    const int xm = cx == 0 ? (g.open_x ? 0 : g.Nx - 1) : cx - 1;
-    const int xp = cx == g.Nx - 1 ? (g.open_x ? cx : 0) : cx + 1;
+    const double* psi = work;
+    const double* jx = work + n;
+    const double* jy = work + 2 * n;
+    const int xm = read_xm(g, cx), xp = read_xp(g, cx);
     int ys = y - 1, yn = y + 1;
     if (g.periodic_y) {
         if (ys < 0) ys += g.Ny;
@@ -1175,18 +1259,11 @@ __global__ __launch_bounds__(256) void moments_pass2(Grid g, Phys k,
         t.d = p - m;
         return t;
     };
-    const Tri<double> pS = row3(ys), pC = row3(y), pN = row3(yn);
-    double Fx = 0.0, Fy = 0.0;
-    if (!(k.flags & kSinglePhase))
-        pair_force(pS, pC, pN, k.negG, Fx, Fy);
-    else
-        Fy = wall_adhesion_y(r, pC.c, k);
-    const double rho = rho_in[i];
-    Fx += rho * drive_at(k, n_t) + (rho - k.rho_v) * k.g_x;
-    Fy += (rho - k.rho_v) * k.g_y;
-    ux_out[i] = (jx[i] + 0.5 * Fx) / rho;
-    uy_out[i] = (jy[i] + 0.5 * Fy) / rho;
-    if (reservoir_node(g, cx, y)) ux_out[i] = uy_out[i] = 0.0;
+    double ux, uy;
+    node_velocity(g, k, cx, y, row3(ys), row3(y), row3(yn), rho_in[i], jx[i], jy[i], n_t, ux,
+                  uy);
+    ux_out[i] = ux;
+    uy_out[i] = uy;
 }
 
 // ---- initial state ----------------------------------------------------------
@@ -1357,27 +1434,30 @@ hipError_t launch_step_batched(const Slot* slots, int n_slots, int total_units, 
 
 template <class S, bool kMX>
 static hipError_t moments_impl(const Grid& g, const Phys& k, const S* f, const float* f0lo,
-                               const S* T, double* scratch, double* rho, double* ux, double* uy,
-                               double* Tout, int64_t n_t, hipStream_t s) {
+                               const S* T, double* work, double* rho, double* ux, double* uy,
+                               double* Tout, int64_t n_t, unsigned long long* n_bad,
+                               hipStream_t s) {
     const int n = g.Nx * g.Ny;
     hipLaunchKernelGGL((moments_pass1<S, kMX>), dim3(blocks_for(n, 256)), dim3(256), 0, s, g, k,
-                       f, f0lo, T, scratch, rho, Tout, (long long)n_t);
+                       f, f0lo, T, work, rho, Tout, (long long)n_t, n_bad);
     hipLaunchKernelGGL(moments_pass2, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, k,
-                       (const double*)scratch, (const double*)rho, ux, uy, (long long)n_t);
+                       (const double*)work, (const double*)rho, ux, uy, (long long)n_t);
     return hipGetLastError();
 }
 
 hipError_t launch_moments_f32(const Grid& g, const Phys& k, const float* f, const float* f0lo,
-                              const float* T, double* scratch, double* rho, double* ux,
-                              double* uy, double* Tout, int64_t n, hipStream_t s) {
+                              const float* T, double* work, double* rho, double* ux,
+                              double* uy, double* Tout, int64_t n, unsigned long long* n_bad,
+                              hipStream_t s) {
     if (f0lo)
-        return moments_impl<float, true>(g, k, f, f0lo, T, scratch, rho, ux, uy, Tout, n, s);
-    return moments_impl<float, false>(g, k, f, nullptr, T, scratch, rho, ux, uy, Tout, n, s);
+        return moments_impl<float, true>(g, k, f, f0lo, T, work, rho, ux, uy, Tout, n, n_bad, s);
+    return moments_impl<float, false>(g, k, f, nullptr, T, work, rho, ux, uy, Tout, n, n_bad, s);
 }
 hipError_t launch_moments_f64(const Grid& g, const Phys& k, const double* f, const double* T,
-                              double* scratch, double* rho, double* ux, double* uy,
-                              double* Tout, int64_t n, hipStream_t s) {
-    return moments_impl<double, false>(g, k, f, nullptr, T, scratch, rho, ux, uy, Tout, n, s);
+                              double* work, double* rho, double* ux, double* uy,
+                              double* Tout, int64_t n, unsigned long long* n_bad, hipStream_t s) {
+    return moments_impl<double, false>(g, k, f, nullptr, T, work, rho, ux, uy, Tout, n, n_bad,
+                                       s);
 }
 
 hipError_t launch_init_f32(const Grid& g, const Phys& k, const double* rho0, float* f,

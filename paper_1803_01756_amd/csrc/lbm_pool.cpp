@@ -45,9 +45,18 @@ struct SlotState {
     int64_t steps_left = 0;  // steps still to enqueue
     bool ready_waited = false;
     bool reported = false;
+    bool failed = false;     // retired early: its state became non-finite
     hipEvent_t ready = nullptr;  // start-up finished (aux stream)
     hipEvent_t done = nullptr;   // last enqueued chunk touching the slot finished (main)
+    // the host copy of the counters after the slot's first chunk has landed:
+    // from then on the mirrored counters are this slot's (an earlier copy may
+    // still carry the counters of a released slot that had the same id)
+    hipEvent_t counted = nullptr;
+    bool counted_recorded = false;
 };
+
+// words per slot in the health-counter array: non-finite readings, clamps
+constexpr int kSlotStat = 2;
 
 size_t slot_bytes(const lbmhost::Layout& L) {
     return 2 * lbmhost::align_up(9 * L.plane * 4) + 2 * lbmhost::align_up(L.plane * 4);
@@ -70,6 +79,12 @@ struct lbm_pool {
     // moment scratch on the aux stream: 7 doubles per node of the largest slot
     double* mom = nullptr;
     size_t mom_cells = 0;
+    // health counters: kSlotStat words per slot id on the device (the step
+    // adds to them), mirrored into pinned host memory after every chunk; the
+    // last word of the array counts non-finite nodes of a read-out
+    unsigned long long* stat_dev = nullptr;
+    unsigned long long* stat_host = nullptr;
+    int stat_cap = 0;
     // device blocks of released slots, reused by later admissions (freeing
     // device memory can stall the device while a batch runs)
     std::vector<std::pair<char*, size_t>> spare;
@@ -105,6 +120,38 @@ lbm_status ensure_mom(lbm_pool* P, size_t cells) {
     P->mom = nullptr;
     PCHK(hipMalloc(reinterpret_cast<void**>(&P->mom), cells * 7 * sizeof(double)));
     P->mom_cells = cells;
+    return LBM_OK;
+}
+
+// Room for the counters of slot ids 0..n-1 (plus the read-out word); a
+// larger array is filled from the old one while no stream uses it.
+lbm_status ensure_stat(lbm_pool* P, int n) {
+    if (n <= P->stat_cap) return LBM_OK;
+    PCHK(hipStreamSynchronize(P->main));
+    PCHK(hipStreamSynchronize(P->aux));
+    const int cap = std::max(n, std::max(64, 2 * P->stat_cap));
+    const size_t words = (size_t)cap * kSlotStat + 1;
+    unsigned long long *d = nullptr, *h = nullptr;
+    PCHK(hipMalloc(reinterpret_cast<void**>(&d), words * sizeof(*d)));
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h), words * sizeof(*h),
+                                 hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemset(d, 0, words * sizeof(*d));
+    if (e == hipSuccess && P->stat_dev)
+        e = hipMemcpy(d, P->stat_dev, (size_t)P->stat_cap * kSlotStat * sizeof(*d),
+                      hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        if (h) (void)hipHostFree(h);
+        return fail(LBM_EDEVICE, "health counters: %s", hipGetErrorString(e));
+    }
+    std::memset(h, 0, words * sizeof(*h));
+    if (P->stat_host)
+        std::memcpy(h, P->stat_host, (size_t)P->stat_cap * kSlotStat * sizeof(*h));
+    if (P->stat_dev) (void)hipFree(P->stat_dev);
+    if (P->stat_host) (void)hipHostFree(P->stat_host);
+    P->stat_dev = d;
+    P->stat_host = h;
+    P->stat_cap = cap;
     return LBM_OK;
 }
 
@@ -178,14 +225,8 @@ lbm_status lbm_pool_admit(lbm_pool* P, const lbm_params* pin, const double* rho0
         return fail(LBM_ENOMEM, "admission refused: %zu + %zu bytes exceed the %zu-byte cap",
                     P->used, need, P->cap);
     const size_t cells = (size_t)p.Nx * p.Ny;
-    const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
-    if (rho0)
-        for (int y = per ? 0 : 1; y < (per ? p.Ny : p.Ny - 1); ++y)
-            for (int x = 0; x < p.Nx; ++x) {
-                const double r = rho0[(size_t)y * p.Nx + x];
-                if (!(r > 0.0 && p.b * r < ((p.flags & LBM_EOS_CS) ? 4.0 : 1.0)))
-                    return fail(LBM_EINVAL, "initial density %g outside the EOS range", r);
-            }
+    st = lbmhost::check_initial(p, rho0);
+    if (st != LBM_OK) return st;
     PCHK(hipSetDevice(P->dev));
     st = ensure_mom(P, cells);
     if (st != LBM_OK) return st;
@@ -196,6 +237,8 @@ lbm_status lbm_pool_admit(lbm_pool* P, const lbm_params* pin, const double* rho0
             id = (int)i;
             break;
         }
+    st = ensure_stat(P, id < 0 ? (int)P->slots.size() + 1 : id + 1);
+    if (st != LBM_OK) return st;
     if (id < 0) {
         P->slots.emplace_back();
         id = (int)P->slots.size() - 1;
@@ -249,12 +292,17 @@ lbm_status lbm_pool_admit(lbm_pool* P, const lbm_params* pin, const double* rho0
     if (rho0) std::copy(rho0, rho0 + cells, r0.begin());
     e = hipMemsetAsync(s.mem, 0, need, P->aux);
     if (e == hipSuccess)
+        e = hipMemsetAsync(P->stat_dev + (size_t)id * kSlotStat, 0,
+                           kSlotStat * sizeof(unsigned long long), P->aux);
+    std::memset(P->stat_host + (size_t)id * kSlotStat, 0, kSlotStat * sizeof(unsigned long long));
+    if (e == hipSuccess)
         e = hipMemcpyAsync(P->mom, r0.data(), cells * sizeof(double), hipMemcpyHostToDevice,
                            P->aux);
     if (e == hipSuccess)
         e = lbmk::launch_init_f32(s.g, s.k, P->mom, s.f[0], nullptr, s.T[0], P->aux);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ready, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.counted, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(s.ready, P->aux);
     // r0 is pageable host memory: the copy has completed when the call
     // returns, so the vector may go out of scope
@@ -270,6 +318,18 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
     if (!P) return fail(LBM_EINVAL, "null pool");
     if (chunk < 1) return fail(LBM_EINVAL, "chunk must be >= 1");
     PCHK(hipSetDevice(P->dev));
+    // A slot whose steps have read a non-finite state (as of the last
+    // counter copy that has landed) is retired: it takes no further steps
+    // and lbm_pool_moments reports it with LBM_EUNSTABLE.  The other slots
+    // are untouched: each reads and writes only its own memory.
+    for (size_t i = 0; i < P->slots.size(); ++i) {
+        SlotState& s = P->slots[i];
+        if (s.used && s.steps_left > 0 && s.counted_recorded &&
+            P->stat_host[i * kSlotStat] != 0ull && hipEventQuery(s.counted) == hipSuccess) {
+            s.steps_left = 0;
+            s.failed = true;
+        }
+    }
     std::vector<int> act;
     for (size_t i = 0; i < P->slots.size(); ++i)
         if (P->slots[i].used && P->slots[i].steps_left > 0) act.push_back((int)i);
@@ -306,6 +366,7 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
         t.cur_T = s.cur_T;
         t.steps_left = take;
         t.unit_begin = units;
+        t.stat = P->stat_dev + (size_t)act[j] * kSlotStat;
         units += s.g.n_units;
         longest = std::max(longest, take);
     }
@@ -322,6 +383,17 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
         s.cur_f ^= (take & 1);
         if (!(s.p.flags & LBM_FREEZE_T)) s.cur_T ^= (take & 1);
         PCHK(hipEventRecord(s.done, P->main));
+    }
+    // the counters as of the end of this chunk, for the next call's check
+    PCHK(hipMemcpyAsync(P->stat_host, P->stat_dev,
+                        P->slots.size() * kSlotStat * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, P->main));
+    for (size_t j = 0; j < act.size(); ++j) {
+        SlotState& s = P->slots[act[j]];
+        if (!s.counted_recorded) {
+            PCHK(hipEventRecord(s.counted, P->main));
+            s.counted_recorded = true;
+        }
     }
     P->steps_enqueued += longest;
     hipEvent_t ev = nullptr;
@@ -371,20 +443,48 @@ lbm_status lbm_pool_moments(lbm_pool* P, int32_t id, double* rho, double* ux, do
     SlotState* s = get_slot(P, id);
     if (!s) return fail(LBM_EINVAL, "no slot %d", id);
     PCHK(hipSetDevice(P->dev));
-    // the slot's state after everything enqueued for it so far
-    PCHK(hipEventRecord(s->done, P->main));
+    // the slot's state after everything enqueued for it so far: `done`
+    // marks the end of the last chunk that stepped it (a slot never stepped
+    // has an unrecorded `done`, which waits for nothing)
     PCHK(hipStreamWaitEvent(P->aux, s->ready, 0));
     PCHK(hipStreamWaitEvent(P->aux, s->done, 0));
     const size_t cells = (size_t)s->p.Nx * s->p.Ny;
     double* m = P->mom;
+    unsigned long long* nb = P->stat_dev + (size_t)P->stat_cap * kSlotStat;
+    PCHK(hipMemsetAsync(nb, 0, sizeof(*nb), P->aux));
     PCHK(lbmk::launch_moments_f32(s->g, s->k, s->f[s->cur_f], nullptr, s->T[s->cur_T], m + 4 * cells,
-                                  m, m + cells, m + 2 * cells, m + 3 * cells, s->n, P->aux));
+                                  m, m + cells, m + 2 * cells, m + 3 * cells, s->n, nb, P->aux));
     double* outs[4] = {rho, ux, uy, T};
     for (int q = 0; q < 4; ++q)
         if (outs[q])
             PCHK(hipMemcpyAsync(outs[q], m + q * cells, cells * sizeof(double),
                                 hipMemcpyDeviceToHost, P->aux));
+    unsigned long long st[kSlotStat + 1];
+    PCHK(hipMemcpyAsync(st, P->stat_dev + (size_t)id * kSlotStat,
+                        kSlotStat * sizeof(unsigned long long), hipMemcpyDeviceToHost, P->aux));
+    PCHK(hipMemcpyAsync(st + kSlotStat, nb, sizeof(*nb), hipMemcpyDeviceToHost, P->aux));
     PCHK(hipStreamSynchronize(P->aux));
+    if (st[0] || st[kSlotStat])
+        return fail(LBM_EUNSTABLE,
+                    "slot %d: non-finite state (%llu node readings by its steps up to n = %lld, "
+                    "%llu nodes at the read-out)%s", id, st[0], (long long)s->n, st[kSlotStat],
+                    s->failed ? "; retired before its last step" : "");
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_slot_health(lbm_pool* P, int32_t id, int64_t* nonfinite,
+                                int64_t* psi_clamps) {
+    SlotState* s = get_slot(P, id);
+    if (!s) return fail(LBM_EINVAL, "no slot %d", id);
+    PCHK(hipSetDevice(P->dev));
+    PCHK(hipStreamWaitEvent(P->aux, s->ready, 0));
+    PCHK(hipStreamWaitEvent(P->aux, s->done, 0));
+    unsigned long long st[kSlotStat];
+    PCHK(hipMemcpyAsync(st, P->stat_dev + (size_t)id * kSlotStat, sizeof(st),
+                        hipMemcpyDeviceToHost, P->aux));
+    PCHK(hipStreamSynchronize(P->aux));
+    if (nonfinite) *nonfinite = (int64_t)st[0];
+    if (psi_clamps) *psi_clamps = (int64_t)st[1];
     return LBM_OK;
 }
 
@@ -399,6 +499,7 @@ lbm_status lbm_pool_release(lbm_pool* P, int32_t id) {
     if (s->mem) P->spare.emplace_back(s->mem, s->block);
     if (s->ready) (void)hipEventDestroy(s->ready);
     if (s->done) (void)hipEventDestroy(s->done);
+    if (s->counted) (void)hipEventDestroy(s->counted);
     P->used -= s->bytes;
     *s = SlotState();
     return LBM_OK;
@@ -420,6 +521,8 @@ lbm_status lbm_pool_destroy(lbm_pool* P) {
     for (hipEvent_t ev : P->spare_events) (void)hipEventDestroy(ev);
     if (P->table_dev) (void)hipFree(P->table_dev);
     if (P->mom) (void)hipFree(P->mom);
+    if (P->stat_dev) (void)hipFree(P->stat_dev);
+    if (P->stat_host) (void)hipHostFree(P->stat_host);
     if (P->aux) (void)hipStreamDestroy(P->aux);
     if (P->owns_main && P->main) (void)hipStreamDestroy(P->main);
     delete P;

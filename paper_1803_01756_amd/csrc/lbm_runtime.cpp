@@ -258,6 +258,8 @@ bool make_layout(const lbm_params& p, Layout* L) {
     o = align_up(o + lbmk::kReduceBlocks * 5 * sizeof(double));
     L->off_out = o;
     o = align_up(o + 8 * sizeof(double));
+    L->off_stat = o;
+    o = align_up(o + kStatWords * sizeof(unsigned long long));
     L->total = o;
     return true;
 }
@@ -305,6 +307,31 @@ lbm_status validate(const lbm_params& p) {
     return LBM_OK;
 }
 
+lbm_status check_initial(const lbm_params& p, const double* rho0) {
+    const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
+    const Eos E = eos_of(p, p.T_c);
+    const double T_in = (p.flags & LBM_OPEN_X) ? inlet_temperature(p) : p.T_0;
+    for (int y = per ? 0 : 1; y < (per ? p.Ny : p.Ny - 1); ++y)
+        for (int x = 0; x < p.Nx; ++x) {
+            const double r = rho0 ? rho0[(size_t)y * p.Nx + x] : p.rho_v;
+            if (!(r > 0.0 && r < E.rmax()))
+                return fail(LBM_EINVAL, "initial density %g at (%d, %d) outside the EOS range",
+                            r, x, y);
+            // the initial temperature of the node (as the start state sets it)
+            const bool frame = x == 0 || x == p.Nx - 1 || (per && (y == 0 || y == p.Ny - 1));
+            double T = p.T_0;
+            if ((p.flags & LBM_OPEN_X) && x == 0) T = T_in;
+            else if ((p.flags & LBM_FRAME_T) && frame) T = p.T_w;
+            const double rr = ((p.flags & LBM_FRAME_RHO) && frame) ? p.rho_frame : r;
+            const double arg = 2.0 * (E.P(rr, T) - rr / 3.0) / p.G;
+            if (!(arg >= 0.0))
+                return fail(LBM_EINVAL,
+                            "initial density %g at (%d, %d) leaves Eq. 10 without a real psi "
+                            "(2 (P - rho/3) / G = %g at T = %g)", rr, x, y, arg, T);
+        }
+    return LBM_OK;
+}
+
 }  // namespace lbmhost
 
 using lbmhost::align_up;
@@ -340,6 +367,9 @@ struct lbm_sim {
     double* scr() const { return reinterpret_cast<double*>(base + L.off_scr); }
     double* part() const { return reinterpret_cast<double*>(base + L.off_part); }
     double* out() const { return reinterpret_cast<double*>(base + L.off_out); }
+    unsigned long long* stat() const {
+        return reinterpret_cast<unsigned long long*>(base + L.off_stat);
+    }
 };
 
 namespace lbmhost {
@@ -487,12 +517,12 @@ hipError_t enqueue_step(lbm_sim* s) {
     const auto off = [](size_t o) { return (unsigned)o; };
     if (s->p.precision == LBM_FP64) {
         lbmk::Bufs<double> b{s->base, span, off(s->L.off_f[fa]), off(s->L.off_f[fb]), 0u, 0u,
-                             off(s->L.off_T[ta]), off(s->L.off_T[tb])};
+                             off(s->L.off_T[ta]), off(s->L.off_T[tb]), s->stat()};
         e = lbmk::launch_step_f64(s->g, s->k, b, s->n, s->stream);
     } else {
         lbmk::Bufs<float> b{s->base, span, off(s->L.off_f[fa]), off(s->L.off_f[fb]),
                             off(s->L.off_lo[fa]), off(s->L.off_lo[fb]),
-                            off(s->L.off_T[ta]), off(s->L.off_T[tb])};
+                            off(s->L.off_T[ta]), off(s->L.off_T[tb]), s->stat()};
         e = lbmk::launch_step_f32(s->g, s->k, b, s->p.precision == LBM_FP32_DEV_MASSEXACT, s->n,
                                   s->stream);
     }
@@ -503,14 +533,37 @@ hipError_t enqueue_step(lbm_sim* s) {
     return hipSuccess;
 }
 
+// The read-out's count of non-finite nodes restarts at every read-out.
 hipError_t enqueue_moments(lbm_sim* s) {
+    unsigned long long* nb = s->stat() + lbmhost::kStatReadout;
+    hipError_t e = hipMemsetAsync(nb, 0, sizeof(*nb), s->stream);
+    if (e != hipSuccess) return e;
     if (s->p.precision == LBM_FP64)
         return lbmk::launch_moments_f64(s->g, s->k, s->f<double>(s->fcur), s->T<double>(s->tcur),
                                         s->scr(), s->mom(0), s->mom(1), s->mom(2), s->mom(3),
-                                        s->n, s->stream);
+                                        s->n, nb, s->stream);
     return lbmk::launch_moments_f32(s->g, s->k, s->f<float>(s->fcur), s->lo(s->fcur),
                                     s->T<float>(s->tcur), s->scr(), s->mom(0), s->mom(1),
-                                    s->mom(2), s->mom(3), s->n, s->stream);
+                                    s->mom(2), s->mom(3), s->n, nb, s->stream);
+}
+
+// Host copy of the health counters, enqueued on the stream (the caller
+// synchronises).
+hipError_t enqueue_stat_copy(lbm_sim* s, unsigned long long* host) {
+    return hipMemcpyAsync(host, s->stat(), lbmhost::kStatWords * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s->stream);
+}
+
+// LBM_EUNSTABLE (with the counts in the message) when any step read a
+// non-finite state or the read-out found one; LBM_OK otherwise.
+lbm_status health_status(const lbm_sim* s, const unsigned long long* st, bool readout) {
+    const unsigned long long bad = st[lbmhost::kStatNonfinite],
+                             now = readout ? st[lbmhost::kStatReadout] : 0ull;
+    if (bad || now)
+        return fail(LBM_EUNSTABLE,
+                    "non-finite state: %llu node readings by the steps up to n = %lld, "
+                    "%llu nodes at the read-out", bad, (long long)s->n, now);
+    return LBM_OK;
 }
 
 size_t state_payload(const lbm_sim* s) {
@@ -620,6 +673,15 @@ lbm_status lbm_eos_latent_heat(const lbm_params* p, double T, double* h_fg) {
     return LBM_OK;
 }
 
+lbm_status lbm_eos_jacob(const lbm_params* p, double T_sat, double T_w, double* Ja) {
+    if (!p || !Ja) return fail(LBM_EINVAL, "null argument");
+    double h;
+    const lbm_status st = lbm_eos_latent_heat(p, T_sat, &h);
+    if (st != LBM_OK) return st;
+    *Ja = p->C_v * (T_sat - T_w) / h;
+    return LBM_OK;
+}
+
 lbm_status lbm_params_resolve(lbm_params* p) {
     if (!p) return fail(LBM_EINVAL, "null params");
     if (!(p->a > 0 && p->b > 0 && p->R > 0)) return fail(LBM_EINVAL, "EOS constants must be positive");
@@ -662,15 +724,10 @@ lbm_status lbm_create(const lbm_params* pin, const double* rho0, void* workspace
     st = validate(p);
     if (st != LBM_OK) return st;
     const size_t cells = (size_t)p.Nx * p.Ny;
-    const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
+    st = lbmhost::check_initial(p, rho0);
+    if (st != LBM_OK) return st;
     std::vector<double> r0(cells, p.rho_v);
     if (rho0) std::copy(rho0, rho0 + cells, r0.begin());
-    for (int y = per ? 0 : 1; y < (per ? p.Ny : p.Ny - 1); ++y)
-        for (int x = 0; x < p.Nx; ++x) {
-            const double r = r0[(size_t)y * p.Nx + x];
-            if (!(r > 0.0 && p.b * r < ((p.flags & LBM_EOS_CS) ? 4.0 : 1.0)))
-                return fail(LBM_EINVAL, "initial density %g at (%d, %d) outside the EOS range", r, x, y);
-        }
 
     lbm_sim* s = new (std::nothrow) lbm_sim();
     if (!s) return fail(LBM_ENOMEM, "host allocation failed");
@@ -740,8 +797,10 @@ lbm_status lbm_step(lbm_sim* s, int64_t n) {
 lbm_status lbm_synchronize(lbm_sim* s) {
     if (!s) return fail(LBM_EINVAL, "null sim");
     HIPCHK(hipSetDevice(s->dev));
+    unsigned long long st[lbmhost::kStatWords];
+    HIPCHK(enqueue_stat_copy(s, st));
     HIPCHK(hipStreamSynchronize(s->stream));
-    return LBM_OK;
+    return health_status(s, st, false);
 }
 
 lbm_status lbm_moments(lbm_sim* s, double* rho, double* ux, double* uy, double* T) {
@@ -753,8 +812,10 @@ lbm_status lbm_moments(lbm_sim* s, double* rho, double* ux, double* uy, double* 
     for (int q = 0; q < 4; ++q)
         if (outs[q])
             HIPCHK(hipMemcpyAsync(outs[q], s->mom(q), bytes, hipMemcpyDeviceToHost, s->stream));
+    unsigned long long st[lbmhost::kStatWords];
+    HIPCHK(enqueue_stat_copy(s, st));
     HIPCHK(hipStreamSynchronize(s->stream));
-    return LBM_OK;
+    return health_status(s, st, true);
 }
 
 lbm_status lbm_reduce(lbm_sim* s, double out[5]) {
@@ -764,9 +825,22 @@ lbm_status lbm_reduce(lbm_sim* s, double out[5]) {
     HIPCHK(lbmk::launch_reduce(s->mom(0), s->mom(1), s->mom(2), s->mom(3), s->p.Nx * s->p.Ny,
                                s->p.C_v, s->part(), s->out(), s->stream));
     HIPCHK(hipMemcpyAsync(out, s->out(), 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    unsigned long long st[lbmhost::kStatWords];
+    HIPCHK(enqueue_stat_copy(s, st));
     HIPCHK(hipStreamSynchronize(s->stream));
     if (out[4] > 0.0) return fail(LBM_EUNSTABLE, "%g non-finite nodes at n = %lld", out[4],
                                   (long long)s->n);
+    return health_status(s, st, true);
+}
+
+lbm_status lbm_health(lbm_sim* s, int64_t* nonfinite, int64_t* psi_clamps) {
+    if (!s) return fail(LBM_EINVAL, "null sim");
+    HIPCHK(hipSetDevice(s->dev));
+    unsigned long long st[lbmhost::kStatWords];
+    HIPCHK(enqueue_stat_copy(s, st));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (nonfinite) *nonfinite = (int64_t)st[lbmhost::kStatNonfinite];
+    if (psi_clamps) *psi_clamps = (int64_t)st[lbmhost::kStatClamps];
     return LBM_OK;
 }
 
@@ -843,6 +917,9 @@ lbm_status lbm_load(lbm_sim* s, const void* host, size_t bytes) {
     if (s->p.precision == LBM_FP32_DEV_MASSEXACT)
         HIPCHK(hipMemcpyAsync(s->base + s->L.off_lo[s->fcur], src, s->L.plane * 4,
                               hipMemcpyHostToDevice, s->stream));
+    // a new state: its health counters start from zero
+    HIPCHK(hipMemsetAsync(s->stat(), 0, lbmhost::kStatWords * sizeof(unsigned long long),
+                          s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     const int seg = s->seg_rows;
     s->p = h.p;
@@ -872,6 +949,10 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps_per_trial, double* best_ms) {
     // snapshot the state on the device; every trial restarts from it
     const size_t fb = 9 * s->L.plane * s->L.esz, tb = s->L.plane * s->L.esz;
     const size_t lb = s->p.precision == LBM_FP32_DEV_MASSEXACT ? s->L.plane * 4 : 0;
+    // the trial steps must not count towards the channel's health counters
+    unsigned long long stat0[lbmhost::kStatWords];
+    HIPCHK(hipMemcpyAsync(stat0, s->stat(), sizeof(stat0), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
     char* snap = nullptr;
     HIPCHK(hipMalloc(reinterpret_cast<void**>(&snap), fb + tb + lb));
     const int64_t n0 = s->n;
@@ -929,6 +1010,8 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps_per_trial, double* best_ms) {
         }
         if (e == hipSuccess) e = restore();
     }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->stat(), stat0, sizeof(stat0), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);

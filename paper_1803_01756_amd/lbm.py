@@ -89,6 +89,10 @@ def lib():
             "lbm_eos_coexistence": (C.c_int, [P, C.c_double, dp, dp, dp]),
             "lbm_eos_pressure": (C.c_int, [P, C.c_double, C.c_double, dp, dp]),
             "lbm_eos_latent_heat": (C.c_int, [P, C.c_double, dp]),
+            "lbm_eos_jacob": (C.c_int, [P, C.c_double, C.c_double, dp]),
+            "lbm_health": (C.c_int, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+            "lbm_pool_slot_health": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64),
+                                               C.POINTER(C.c_int64)]),
             "lbm_workspace_bytes": (C.c_size_t, [P]),
             "lbm_create": (C.c_int, [P, dp, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "lbm_step": (C.c_int, [vp, C.c_int64]),
@@ -133,13 +137,16 @@ def lib():
 def exported_symbols():
     """Names the header declares; the CPU tests check the library has them."""
     return ["lbm_params_default", "lbm_params_resolve", "lbm_eos_critical", "lbm_eos_critical_cs",
-            "lbm_eos_coexistence", "lbm_eos_pressure", "lbm_eos_latent_heat",
+            "lbm_eos_coexistence", "lbm_eos_pressure", "lbm_eos_latent_heat", "lbm_eos_jacob",
             "lbm_workspace_bytes", "lbm_create", "lbm_step",
-            "lbm_moments", "lbm_reduce", "lbm_synchronize", "lbm_destroy", "lbm_time",
+            "lbm_moments", "lbm_reduce", "lbm_synchronize",
+            "lbm_health", "lbm_destroy",
+            "lbm_time",
             "lbm_get_params", "lbm_last_error", "lbm_state_bytes", "lbm_save", "lbm_load",
             "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_bandwidth_probe",
             "lbm_pool_footprint", "lbm_pool_create", "lbm_pool_admit", "lbm_pool_run",
-            "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_release", "lbm_pool_destroy",
+            "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_slot_health", "lbm_pool_release",
+            "lbm_pool_destroy",
             "lbm_pool_info", "lbm_pool_slot_time", "lbm_pool_set_launch",
             "lbm_pool_synchronize", "lbm_pool_wait"]
 
@@ -196,9 +203,14 @@ def lbm_eos_latent_heat(p: lbm_params, T: float) -> float:
     return h.value
 
 
-def jacob_number(p: lbm_params, T_sat: float, T_w: float) -> float:
-    """Eq. 20: Ja = C_v (T_sat - T_w) / h_fg(T_sat)."""
-    return p.C_v * (T_sat - T_w) / lbm_eos_latent_heat(p, T_sat)
+def lbm_eos_jacob(p: lbm_params, T_sat: float, T_w: float) -> float:
+    """Eq. 20: Ja = C_v (T_sat - T_w) / h_fg(T_sat) (computed by the library)."""
+    ja = C.c_double()
+    _check(lib().lbm_eos_jacob(C.byref(p), T_sat, T_w, C.byref(ja)))
+    return ja.value
+
+
+jacob_number = lbm_eos_jacob
 
 
 def lbm_eos_pressure(p: lbm_params, rho: float, T: float):
@@ -245,6 +257,13 @@ def lbm_reduce(h: int, check: bool = True):
 
 def lbm_synchronize(h: int):
     _check(lib().lbm_synchronize(C.c_void_p(h)))
+
+
+def lbm_health(h: int):
+    """(non-finite readings, psi clamps) counted by the steps so far."""
+    a, b = C.c_int64(), C.c_int64()
+    _check(lib().lbm_health(C.c_void_p(h), C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def lbm_destroy(h: int):
@@ -329,8 +348,14 @@ class Sim:
         return lbm_reduce(self.h, check)
 
     def synchronize(self):
-        """Wait for the enqueued steps (lbm_synchronize)."""
+        """Wait for the enqueued steps (lbm_synchronize); a non-finite state
+        read by a step raises LBMError(LBM_EUNSTABLE)."""
         lbm_synchronize(self.h)
+
+    def health(self):
+        """(non-finite node readings, psi clamps) counted by the steps so far
+        (lbm_health)."""
+        return lbm_health(self.h)
 
     @property
     def n(self) -> int:
@@ -428,6 +453,14 @@ class Pool:
         outs = [np.empty((Ny, Nx)) for _ in range(4)]
         _check(lib().lbm_pool_moments(C.c_void_p(self.h), int(slot), *[_dp(o) for o in outs]))
         return tuple(outs)
+
+    def slot_health(self, slot: int):
+        """(non-finite node readings, psi clamps) of a slot
+        (lbm_pool_slot_health)."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().lbm_pool_slot_health(C.c_void_p(self.h), int(slot), C.byref(a),
+                                          C.byref(b)))
+        return a.value, b.value
 
     def release(self, slot: int):
         """Free a slot's memory for later admissions (lbm_pool_release)."""

@@ -8,7 +8,9 @@
                   (footprint against a byte cap), are stepped together in
                   chunks while later requests keep arriving, and return
                   rho, u, T on the host when they finish.  Latency is arrival
-                  to results on the host.
+                  to results on the host.  A request whose state turns
+                  non-finite is retired by the pool and returns an error
+                  (``Request.error``) instead of results; the loop goes on.
 
 The scheduling logic works against any object with the ``lbm.Pool``
 interface, so it can be exercised on the CPU with a fake pool.
@@ -35,6 +37,7 @@ class Request:
     finished: float = -1.0
     slot: int = -1
     result: tuple = field(default=None, repr=False)
+    error: str = ""         # set when the request was retired with a non-finite state
 
 
 def channel_request(d: dict, steps: int, rid: int = 0) -> tuple:
@@ -129,7 +132,12 @@ def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.per
         done = pool.poll()
         for slot in done:
             r = by_slot.pop(slot)
-            r.result = pool.moments(slot, r.params.Nx, r.params.Ny)
+            try:
+                r.result = pool.moments(slot, r.params.Nx, r.params.Ny)
+            except lbm.LBMError as e:
+                if e.status != lbm.LBM_EUNSTABLE:
+                    raise
+                r.error = str(e)  # retired: its state became non-finite
             r.finished = clock() - t0
             pool.release(slot)
             finished += 1

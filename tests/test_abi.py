@@ -196,4 +196,56 @@ def test_null_handles_are_refused_without_a_device(L):
     assert f.lbm_pool_set_launch(None, 26) == EINVAL
     assert f.lbm_pool_synchronize(None) == EINVAL
     assert f.lbm_pool_create(0, None, None) == EINVAL
+    assert f.lbm_health(None, None, None) == EINVAL
+    assert f.lbm_pool_slot_health(None, 0, None, None) == EINVAL
     assert len(f.lbm_last_error()) > 0
+
+
+def test_jacob_number_matches_oracle(L, orc):
+    """Eq. 20 computed by the library (lbm_eos_jacob) against the oracle's."""
+    p = lbm.lbm_params_resolve(lbm.lbm_params_default())
+    q = orc.default_params()
+    for ts, tw in ((0.86, 0.80), (0.86, 0.56), (0.7, 0.65)):
+        ja = lbm.lbm_eos_jacob(p, ts * p.T_c, tw * p.T_c)
+        assert ja == pytest.approx(orc.jacob(q, ts * p.T_c, tw * p.T_c), rel=1e-9)
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_eos_jacob(p, 1.01 * p.T_c, 0.8 * p.T_c)
+
+
+@pytest.mark.parametrize("where", ["fluid", "frame_t"])
+def test_create_refuses_initial_density_without_real_psi(L, orc, where):
+    """An initial density for which the Eq. 10 argument 2 (P - rho/3) / G is
+    negative at the node's initial temperature (P - rho/3 > 0 with G < 0,
+    first at rho = 8.97 at 0.86 T_c) is refused with LBM_EINVAL before any
+    device call; a density just below the limit is not the reason for a
+    refusal.  The limit is located with the oracle's EOS.  With FRAME_T the
+    frame starts at T_w, so the limit there is the one at T_w."""
+    import ctypes as C
+    flags = lbm.LBM_FRAME_T if where == "frame_t" else 0
+    p = configs.channel_params(16, 8, 90.0, 0.60, 0.0, 0.0, lbm.LBM_FP32_DEV, flags)
+    q = orc.default_params()
+    T = p.T_w if where == "frame_t" else p.T_0
+    lo, hi = 5.0, 10.4
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        if orc.peos(q, mid, T) - mid / 3.0 > 0:
+            hi = mid
+        else:
+            lo = mid
+    x = 0 if where == "frame_t" else 7
+    for rho, expect_refusal in ((hi * (1 + 1e-6), True), (lo * (1 - 1e-6), False)):
+        r0 = np.full((8, 16), p.rho_v)
+        r0[3, x] = rho
+        h = C.c_void_p()
+        st = L.lbm_create(C.byref(p), r0.ctypes.data_as(C.POINTER(C.c_double)), None, 0, None,
+                          C.byref(h))
+        msg = L.lbm_last_error().decode()
+        if expect_refusal:
+            assert st == lbm.LBM_EINVAL and "Eq. 10" in msg, msg
+            assert h.value is None
+        else:
+            # on this machine the call then fails at the device (or succeeds
+            # on a GPU machine); either way not for the density
+            assert "Eq. 10" not in msg
+            if st == lbm.LBM_OK:
+                L.lbm_destroy(h)

@@ -235,9 +235,10 @@ def test_nonfinite_state_is_reported():
     blob[mid - 8192: mid] = b"\xff" * 8192
     s.load(bytes(blob))
     s.step(3)
-    with pytest.raises(lbm.LBMError) as ei:
-        s.reduce()
-    assert ei.value.status == lbm.LBM_EUNSTABLE
+    for call in (s.synchronize, s.reduce):
+        with pytest.raises(lbm.LBMError) as ei:
+            call()
+        assert ei.value.status == lbm.LBM_EUNSTABLE
     s.close()
 
 

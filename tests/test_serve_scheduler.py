@@ -4,7 +4,7 @@ scripted cost per chunk and a simulated clock: no GPU involved."""
 import numpy as np
 import pytest
 
-from paper_1803_01756_amd import serve
+from paper_1803_01756_amd import lbm, serve
 
 
 class FakeParams:
@@ -63,6 +63,8 @@ class FakePool:
         return out
 
     def moments(self, sid, Nx, Ny):
+        if self.slots[sid].get("poisoned"):
+            raise lbm.LBMError(lbm.LBM_EUNSTABLE, "slot %d: non-finite state" % sid)
         return ("result", sid)
 
     def release(self, sid):
@@ -130,3 +132,25 @@ def test_request_larger_than_the_cap_is_refused():
             serve.Request(1, 0.01, FakeParams(100, 100), None, 100)]
     with pytest.raises(ValueError):
         serve.serve(reqs, pool, chunk=50, clock=clk, sleep=clk.sleep)
+
+
+def test_retired_request_returns_an_error_and_the_loop_goes_on():
+    """A slot that the pool retired with a non-finite state (lbm_pool_moments
+    gives LBM_EUNSTABLE) ends its request with an error; every other request
+    still gets its results."""
+    clk = FakeClock()
+    pool = FakePool(cap=10 ** 6, clock=clk)
+    admit = pool.admit
+
+    def admit_poisoning_rid3(p, rho0, steps):
+        sid = admit(p, rho0, steps)
+        if sid is not None and len(pool.admit_log) == 4:
+            pool.slots[sid]["poisoned"] = True
+        return sid
+
+    pool.admit = admit_poisoning_rid3
+    reqs = _reqs(12, 20.0, [(256, 32), (512, 64)], [2000, 5000])
+    serve.serve(reqs, pool, chunk=500, clock=clk, sleep=clk.sleep)
+    bad = [r for r in reqs if r.error]
+    assert len(bad) == 1 and bad[0].result is None and "non-finite" in bad[0].error
+    assert all(r.result == ("result", r.slot) for r in reqs if not r.error)
