@@ -127,19 +127,21 @@ def run_config(p, rho0, steps, warmup, tune=True, seg_rows=0):
     return ms, wall_ms, seg, waves, red
 
 
-def oracle_mlups(p, rho0, steps):
-    """FP64 oracle (single thread, as built) on the full grid for `steps`."""
+def oracle_mlups(p, rho0, steps, omp=False):
+    """FP64 oracle on the full grid for `steps`: the sequential build, or
+    with omp the OpenMP-over-rows build on OMP_NUM_THREADS threads (bitwise
+    the same results).  Returns (MLUPS, seconds, threads)."""
     from oracle import oracle as O
     names = dict(T_c="Tc", G_w="Gw", psi_w="psiw", C_v="Cv", lambda_="lam", T_0="T0",
                  T_w="Tw", g_x="gx", g_y="gy")
     op = O.make_params(**{names.get(k, k): v for k, v in p.as_dict().items()
                           if k not in ("rho_ref", "precision")})
-    sim = O.Sim(op, rho0)
+    sim = O.Sim(op, rho0, omp=omp)
     sim.step(1)  # first-touch of the scratch fields outside the timing
     t0 = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t0
-    return fluid_nodes(p) * steps / dt / 1e6, dt
+    return fluid_nodes(p) * steps / dt / 1e6, dt, O.threads(omp)
 
 
 def batch_and_serve(args):
@@ -410,6 +412,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-steps-omp", type=int, default=40,
+                    help="oracle steps on the full grid for the all-threads CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=6,
                     help="oracle steps on the full grid for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -486,11 +490,17 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("CPU oracle: %d steps on the full 8192x512 grid" % args.cpu_steps)
-        cm, dt = oracle_mlups(p, rho0, args.cpu_steps)
-        cpu = dict(value=round(cm, 3), unit="MLUPS", cores=1, kind="oracle",
-                   sample="FP64 oracle, single thread, %d steps of the full 8192x512 grid "
-                          "(%.1f s)" % (args.cpu_steps, dt),
+        log("CPU oracle, all host threads: %d steps on the full 8192x512 grid"
+            % args.cpu_steps_omp)
+        cm_n, dt_n, thr = oracle_mlups(p, rho0, args.cpu_steps_omp, omp=True)
+        log("CPU oracle, one thread: %d steps on the full 8192x512 grid" % args.cpu_steps)
+        cm, dt, _ = oracle_mlups(p, rho0, args.cpu_steps)
+        cpu = dict(value=round(cm_n, 3), unit="MLUPS", cores=thr, kind="oracle",
+                   sample="FP64 oracle, OpenMP over rows on %d threads, %d steps of the full "
+                          "8192x512 grid (%.1f s)" % (thr, args.cpu_steps_omp, dt_n),
+                   single_thread=dict(value=round(cm, 3), unit="MLUPS", cores=1,
+                                      sample="the sequential build, %d steps of the full "
+                                             "8192x512 grid (%.1f s)" % (args.cpu_steps, dt)),
                    host=host_info())
 
     line = {

@@ -79,6 +79,21 @@
  *    at the same RK stage.
  */
 #define _USE_MATH_DEFINES
+/* Row sweeps may run on several threads (OpenMP over rows) when built with
+ * -fopenmp; every sweep writes each node's values from the previous fields
+ * only, and the one cross-node sum (the psi clamp count) is an integer, so
+ * the threaded build gives bitwise the same results.  Without -fopenmp the
+ * pragmas are absent and the oracle is the plain sequential program. */
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_PRAGMA(x) _Pragma(#x)
+#define ORC_ROWS_PARALLEL ORC_PRAGMA(omp parallel for schedule(static))
+#define ORC_ROWS_PARALLEL_REDUCE(v) ORC_PRAGMA(omp parallel for schedule(static) reduction(+ : v))
+#else
+#define ORC_ROWS_PARALLEL
+#define ORC_ROWS_PARALLEL_REDUCE(v)
+#endif
+
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -549,6 +564,15 @@ void orc_sim_set_time(orc_sim* s, int64_t n) { s->n = n; }
 int64_t orc_sim_time(const orc_sim* s) { return s->n; }
 int64_t orc_sim_psi_clamps(const orc_sim* s) { return s->psi_clamps; }
 
+/* threads a row sweep uses (1 in the sequential build) */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* OPEN_X boundary densities.  Inlet: the vapour-branch root of
  * P_EOS(rho, T_in) = p0 (1 + p_amp sin(2 pi n / p_period)) (p_period <= 0:
  * the constant p0 (1 + p_amp)), by bisection below the vapour spinodal (the
@@ -607,6 +631,8 @@ static void macroscopic(orc_sim* s) {
     const orc_params* p = &s->p;
     const int Nx = p->Nx, Ny = p->Ny;
     /* S1 (Eq. 13) and S2 (Eq. 10-11) */
+    int64_t clamps = 0;
+    ORC_ROWS_PARALLEL_REDUCE(clamps)
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
             size_t c = IDX(p, x, y);
@@ -616,13 +642,15 @@ static void macroscopic(orc_sim* s) {
             if (reservoir(p, x, y)) r = p->rho_frame;
             s->rho[c] = r;
             double arg = 2.0 * (orc_peos(p, r, s->T[c]) - r / 3.0) / p->G;
-            if (!(arg > 0.0)) s->psi_clamps++;
+            if (!(arg > 0.0)) clamps++;
             s->psi[c] = orc_psi(p, r, s->T[c]);
         }
+    s->psi_clamps += clamps;
     /* S3: Eq. 9 (fluid neighbours), Eq. 14 (solid neighbours), Eq. 15 and
      * the oscillating drive; S4: Eq. 13 velocity */
     double drive = 0.0;
     if (p->period > 0.0) drive = p->g_osc * sin(2.0 * 3.14159265358979323846 * (double)s->n / p->period);
+    ORC_ROWS_PARALLEL
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
             size_t c = IDX(p, x, y);
@@ -686,6 +714,7 @@ static double cv_at(const orc_params* p, double rho) {
  * rows), with rho and u frozen at time level n. */
 static void heat_rhs(const orc_sim* s, const double* Ts, double* out) {
     const orc_params* p = &s->p;
+    ORC_ROWS_PARALLEL
     for (int y = 0; y < p->Ny; ++y)
         for (int x = 0; x < p->Nx; ++x) {
             size_t c = IDX(p, x, y);
@@ -735,6 +764,7 @@ static void step_once(orc_sim* s) {
     if (p->flags & ORC_OPEN_X) open_ends(s); /* S0: open ends at level n */
     macroscopic(s);
     /* S5-S6: collision on every fluid node into fpost */
+    ORC_ROWS_PARALLEL
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
             if (is_solid(p, y)) continue;
@@ -762,12 +792,14 @@ static void step_once(orc_sim* s) {
         for (size_t c = 0; c < N; ++c) s->acc[c] = 0.0;
         for (int st = 0; st < 4; ++st) {
             heat_rhs(s, s->Ts, s->h);
+            ORC_ROWS_PARALLEL
             for (int y = 0; y < Ny; ++y)
                 for (int x = 0; x < Nx; ++x) {
                     size_t c = IDX(p, x, y);
                     if (t_held(p, x, y)) continue;
                     s->acc[c] += wts[st] * s->h[c];
                 }
+            ORC_ROWS_PARALLEL
             for (int y = 0; y < Ny; ++y)
                 for (int x = 0; x < Nx; ++x) {
                     size_t c = IDX(p, x, y);
@@ -775,6 +807,7 @@ static void step_once(orc_sim* s) {
                     s->Ts[c] = s->T[c] + cst[st] * s->h[c];
                 }
         }
+        ORC_ROWS_PARALLEL
         for (int y = 0; y < Ny; ++y)
             for (int x = 0; x < Nx; ++x) {
                 size_t c = IDX(p, x, y);
@@ -783,6 +816,9 @@ static void step_once(orc_sim* s) {
     }
     /* S8: streaming (Eq. 12) with half-way bounce-back at solid nodes */
     for (size_t k = 0; k < 9 * N; ++k) s->f[k] = 0.0;
+    /* every (plane, target node) has exactly one source node, so the rows
+     * may be streamed concurrently */
+    ORC_ROWS_PARALLEL
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
             if (is_solid(p, y)) continue;

@@ -19,6 +19,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
+# the same source built with OpenMP over the rows of every sweep (bitwise the
+# same results; used to time the oracle on all host cores)
+LIB_OMP = os.path.join(HERE, "liblbm_oracle_omp.so")
 
 FREEZE_T = 1
 SINGLE_PHASE = 2
@@ -31,14 +34,17 @@ PHASE_PROPS = 128
 TOP_MIXED = 256
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
+def build(force: bool = False, omp: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math); omp: the
+    OpenMP-over-rows build."""
+    out = LIB_OMP if omp else LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+        tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC"] + (["-fopenmp"] if omp else []) +
+            ["-o", tmp, SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class OrcParams(C.Structure):
@@ -66,13 +72,15 @@ class OrcParams(C.Structure):
 
 
 _lib = None
+_lib_omp = None
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        build()
-        L = C.CDLL(LIB)
+def lib(omp: bool = False):
+    """The sequential oracle library, or with omp the OpenMP build."""
+    global _lib, _lib_omp
+    if (_lib_omp if omp else _lib) is None:
+        build(omp=omp)
+        L = C.CDLL(LIB_OMP if omp else LIB)
         dp = C.POINTER(C.c_double)
         P = C.POINTER(OrcParams)
         L.orc_matrix_M.argtypes = [dp]
@@ -106,8 +114,17 @@ def lib():
         L.orc_sim_psi_clamps.restype = C.c_int64
         L.orc_sim_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_sim_moments.argtypes = [C.c_void_p] + [dp] * 6
-        _lib = L
-    return _lib
+        L.orc_threads.restype = C.c_int
+        if omp:
+            _lib_omp = L
+        else:
+            _lib = L
+    return _lib_omp if omp else _lib
+
+
+def threads(omp: bool = True) -> int:
+    """Threads a row sweep of that build uses (OMP_NUM_THREADS)."""
+    return int(lib(omp).orc_threads())
 
 
 def _dp(a: np.ndarray):
@@ -244,55 +261,59 @@ def default_params(Nx: int = 128, Ny: int = 32, **kw) -> OrcParams:
 
 class Sim:
     """Full-field FP64 solver.  State after n steps: f_i(x, n) (post-stream)
-    and T(x, n).  Arrays are indexed [y, x]."""
+    and T(x, n).  Arrays are indexed [y, x].  omp: run on the OpenMP build
+    (all threads of OMP_NUM_THREADS; bitwise the same results)."""
 
-    def __init__(self, p: OrcParams, rho0: np.ndarray | None = None, rho_uniform: float = 1.0):
+    def __init__(self, p: OrcParams, rho0: np.ndarray | None = None, rho_uniform: float = 1.0,
+                 omp: bool = False):
         self.p = p
         self.Nx, self.Ny = p.Nx, p.Ny
-        self.h = lib().orc_sim_new(C.byref(p))
+        self._L = lib(omp)
+        self.h = self._L.orc_sim_new(C.byref(p))
         if not self.h:
             raise ValueError("invalid oracle grid")
         if rho0 is not None:
             r = np.ascontiguousarray(rho0, dtype=np.float64).reshape(self.Ny, self.Nx)
-            lib().orc_sim_init(self.h, _dp(r), 0.0)
+            self._L.orc_sim_init(self.h, _dp(r), 0.0)
         else:
-            lib().orc_sim_init(self.h, None, rho_uniform)
+            self._L.orc_sim_init(self.h, None, rho_uniform)
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h and _lib is not None:
-            _lib.orc_sim_free(h)
+        L = getattr(self, "_L", None)
+        if h and L is not None:
+            L.orc_sim_free(h)
             self.h = None
 
     @property
     def n(self) -> int:
-        return lib().orc_sim_time(self.h)
+        return self._L.orc_sim_time(self.h)
 
     @property
     def psi_clamps(self) -> int:
-        return lib().orc_sim_psi_clamps(self.h)
+        return self._L.orc_sim_psi_clamps(self.h)
 
     def step(self, nsteps: int = 1):
-        lib().orc_sim_step(self.h, int(nsteps))
+        self._L.orc_sim_step(self.h, int(nsteps))
 
     def set_f(self, f: np.ndarray):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, self.Ny, self.Nx)
-        lib().orc_sim_set_f(self.h, _dp(f))
+        self._L.orc_sim_set_f(self.h, _dp(f))
 
     def get_f(self) -> np.ndarray:
         f = np.zeros((9, self.Ny, self.Nx))
-        lib().orc_sim_get_f(self.h, _dp(f))
+        self._L.orc_sim_get_f(self.h, _dp(f))
         return f
 
     def set_T(self, T: np.ndarray):
         T = np.ascontiguousarray(T, dtype=np.float64).reshape(self.Ny, self.Nx)
-        lib().orc_sim_set_T(self.h, _dp(T))
+        self._L.orc_sim_set_T(self.h, _dp(T))
 
     def set_time(self, n: int):
-        lib().orc_sim_set_time(self.h, int(n))
+        self._L.orc_sim_set_time(self.h, int(n))
 
     def moments(self):
         """(rho, ux, uy, T, Fx, Fy) at the current time level, each [Ny, Nx]."""
         outs = [np.zeros((self.Ny, self.Nx)) for _ in range(6)]
-        lib().orc_sim_moments(self.h, *[_dp(o) for o in outs])
+        self._L.orc_sim_moments(self.h, *[_dp(o) for o in outs])
         return tuple(outs)
