@@ -230,6 +230,24 @@ lbm_status lbm_moments(lbm_sim* sim, double* rho, double* ux, double* uy, double
  * state. */
 lbm_status lbm_reduce(lbm_sim* sim, double out[5]);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * totals of lbm_reduce, out_dev[0..4] (sum rho, sum rho u_x, sum rho u_y,
+ * sum rho C_v T, non-finite nodes) at the current time level, written to
+ * caller-owned device memory (5 doubles, 8-byte aligned) by work enqueued
+ * on the simulation's stream; the call returns without waiting.  The
+ * values equal lbm_reduce's up to the FP64 summation order (one pass over
+ * tiles of 64 x 4 nodes instead of two passes through the moment arrays).
+ * It allocates nothing, does not synchronise and issues no memset: the
+ * block partials live in a 40 KiB array the library holds on every GPU it
+ * runs on until the process ends (at most 1024 blocks, a grid-stride loop
+ * covers any grid the library accepts).  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (two streams, two threads) race
+ * and must be ordered by the caller.  No status from the state: read
+ * out_dev[4] for the non-finite count.  LBM_EINVAL for a null or unaligned
+ * pointer, LBM_EDEVICE for a launch error. */
+lbm_status lbm_reduce_noalloc(lbm_sim* sim, double* out_dev);
+
 /* Wait for all enqueued work.  LBM_EDEVICE on a device error,
  * LBM_EUNSTABLE when some completed step read a non-finite rho or T. */
 lbm_status lbm_synchronize(lbm_sim* sim);

@@ -145,6 +145,18 @@ hipError_t launch_reduce(const double* rho, const double* ux, const double* uy,
                          const double* T, int n, double Cv, double* partials, double* out,
                          hipStream_t s);
 
+// The totals of launch_reduce (out_dev[5], device memory) computed in one
+// pass from the stored state at time level n_t, with the block partials in
+// the library's file-scope scratch array (kStaticReduceBlocks blocks at
+// most; no allocation, no clearing): the allocation-free reduction.  Calls
+// that overlap on one device share that scratch and race.
+constexpr int kStaticReduceBlocks = 1024;
+hipError_t launch_reduce_state_f32(const Grid& g, const Phys& k, const float* f,
+                                   const float* f0lo, const float* T, double Cv, int64_t n_t,
+                                   double* out_dev, hipStream_t s);
+hipError_t launch_reduce_state_f64(const Grid& g, const Phys& k, const double* f, const double* T,
+                                   double Cv, int64_t n_t, double* out_dev, hipStream_t s);
+
 // Plain device copy of bytes (a multiple of 16) for the bandwidth probe.
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 

@@ -23,6 +23,9 @@
 // (5 extra leading and trailing iterations).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "lbm_internal.h"
 
 namespace lbmk {
@@ -1357,6 +1360,87 @@ __global__ __launch_bounds__(64) void reduce_pass2(const double* __restrict__ pa
     }
 }
 
+// ---- one-pass reduction from the state (allocation-free entry point) ------
+// A block takes tiles of 64 columns x 4 rows in a fixed order (tile
+// blockIdx.x, then every gridDim.x-th).  For a tile it evaluates psi on the
+// tile and its one-node ring into LDS (66 x 6 nodes, the ring recomputed),
+// then every node of the tile its u from its own state and the psi of its
+// neighbours, and adds rho, rho u_x, rho u_y, rho C_v T and the non-finite
+// count in FP64.  Block totals go to part[5 * blockIdx.x + q] (every entry
+// written, nothing needs clearing); reduce_pass2 sums them in block order.
+constexpr int kTileW = 64, kTileH = 4;
+constexpr int kRingW = kTileW + 2, kRingH = kTileH + 2;
+
+template <class S, bool kMX>
+__global__ __launch_bounds__(256) void reduce_state_kernel(Grid g, Phys k,
+                                                           const S* __restrict__ f,
+                                                           const float* __restrict__ f0lo,
+                                                           const S* __restrict__ T, double Cv,
+                                                           long long n_t,
+                                                           double* __restrict__ part) {
+    __shared__ double psi_t[kRingH][kRingW];
+    const int tiles_x = (g.Nx + kTileW - 1) / kTileW;
+    const int tiles = tiles_x * ((g.Ny + kTileH - 1) / kTileH);
+    const int tx = threadIdx.x & (kTileW - 1), ty = threadIdx.x >> 6;
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int x0 = (t % tiles_x) * kTileW, y0 = (t / tiles_x) * kTileH;
+        __syncthreads();  // the previous tile's readers are done
+        for (int e = threadIdx.x; e < kRingW * kRingH; e += blockDim.x) {
+            const int ex = e % kRingW, ey = e / kRingW;
+            // ring columns map as the read-out's neighbours do (periodic or
+            // the end column past an open end); entries no node reads are
+            // left unset
+            int cx = x0 - 1 + ex;
+            if (cx < 0) cx = read_xm(g, 0);
+            else if (cx >= g.Nx) cx = cx == g.Nx ? read_xp(g, g.Nx - 1) : -1;
+            int y = y0 - 1 + ey;
+            if (g.periodic_y) y = y < 0 ? y + g.Ny : (y >= g.Ny ? y - g.Ny : y);
+            else if (y < 0 || y >= g.Ny) y = -1;
+            if (cx >= 0 && y >= 0 && y < g.Ny)
+                psi_t[ey][ex] = node_state<S, kMX>(g, k, f, f0lo, T, cx, y, n_t).psi;
+        }
+        __syncthreads();
+        const int cx = x0 + tx, y = y0 + ty;
+        if (cx < g.Nx && y < g.Ny) {
+            const NodeState o = node_state<S, kMX>(g, k, f, f0lo, T, cx, y, n_t);
+            if (o.fluid) {
+                auto row3 = [&](int ey) {
+                    const double m = psi_t[ey][tx], p = psi_t[ey][tx + 2];
+                    Tri<double> r;
+                    r.c = psi_t[ey][tx + 1];
+                    r.a = p + m;
+                    r.d = p - m;
+                    return r;
+                };
+                double ux, uy;
+                node_velocity(g, k, cx, y, row3(ty), row3(ty + 1), row3(ty + 2), o.rho, o.jx,
+                              o.jy, n_t, ux, uy);
+                if (!(isfinite(o.rho) && isfinite(ux) && isfinite(uy) && isfinite(o.T))) {
+                    s[4] += 1.0;
+                } else {
+                    s[0] += o.rho;
+                    s[1] += o.rho * ux;
+                    s[2] += o.rho * uy;
+                    s[3] += o.rho * Cv * o.T;
+                }
+            }
+        }
+    }
+    __shared__ double red[4][5];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const double v = wave_sum(s[q]);
+        if (ln == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int q = threadIdx.x;
+        part[blockIdx.x * 5 + q] = ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q]));
+    }
+}
+
 inline int blocks_for(int n, int bs) { return (n + bs - 1) / bs; }
 
 // ---- plain copy for the bandwidth probe -----------------------------------
@@ -1477,6 +1561,64 @@ hipError_t launch_init_f64(const Grid& g, const Phys& k, const double* rho0, dou
     hipLaunchKernelGGL((init_kernel<double, false>), dim3(blocks_for(n, 256)), dim3(256), 0, s,
                        g, k, rho0, f, (float*)nullptr, T);
     return hipGetLastError();
+}
+
+// ---- allocation-free reduction: file-scope scratch -------------------------
+// Block partials of reduce_state_kernel for callers that cannot allocate:
+// kStaticReduceBlocks x 5 doubles (40 KiB) per GPU, held until the process
+// ends.  Host code never uses the array's name as an address: each device's
+// copy is resolved once with hipGetSymbolAddress (that device current) and
+// the resolved pointer is passed to the kernels.
+static __device__ __align__(256) double scratch[kStaticReduceBlocks * 5];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// this device's copy of `scratch` (resolved on its first use)
+hipError_t scratch_on_current_device(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<double*>(g_scratch_ptr[dev]);
+    return hipSuccess;
+}
+
+template <class S, bool kMX>
+hipError_t reduce_state_impl(const Grid& g, const Phys& k, const S* f, const float* f0lo,
+                             const S* T, double Cv, int64_t n_t, double* out_dev,
+                             hipStream_t s) {
+    double* part = nullptr;
+    hipError_t e = scratch_on_current_device(&part);
+    if (e != hipSuccess) return e;
+    const long long tiles = (long long)((g.Nx + kTileW - 1) / kTileW) *
+                            ((g.Ny + kTileH - 1) / kTileH);
+    const int nb = (int)std::min<long long>(tiles, kStaticReduceBlocks);
+    hipLaunchKernelGGL((reduce_state_kernel<S, kMX>), dim3(nb), dim3(kTileW * kTileH), 0, s, g,
+                       k, f, f0lo, T, Cv, (long long)n_t, part);
+    hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(64), 0, s, (const double*)part, nb, out_dev);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_reduce_state_f32(const Grid& g, const Phys& k, const float* f,
+                                   const float* f0lo, const float* T, double Cv, int64_t n_t,
+                                   double* out_dev, hipStream_t s) {
+    if (f0lo) return reduce_state_impl<float, true>(g, k, f, f0lo, T, Cv, n_t, out_dev, s);
+    return reduce_state_impl<float, false>(g, k, f, nullptr, T, Cv, n_t, out_dev, s);
+}
+hipError_t launch_reduce_state_f64(const Grid& g, const Phys& k, const double* f, const double* T,
+                                   double Cv, int64_t n_t, double* out_dev, hipStream_t s) {
+    return reduce_state_impl<double, false>(g, k, f, nullptr, T, Cv, n_t, out_dev, s);
 }
 
 hipError_t launch_reduce(const double* rho, const double* ux, const double* uy, const double* T,

@@ -833,6 +833,22 @@ lbm_status lbm_reduce(lbm_sim* s, double out[5]) {
     return health_status(s, st, true);
 }
 
+lbm_status lbm_reduce_noalloc(lbm_sim* s, double* out_dev) {
+    if (!s || !out_dev) return fail(LBM_EINVAL, "null argument");
+    if ((reinterpret_cast<uintptr_t>(out_dev) & 7u) != 0)
+        return fail(LBM_EINVAL, "out_dev must be 8-byte aligned");
+    HIPCHK(hipSetDevice(s->dev));
+    if (s->p.precision == LBM_FP64)
+        HIPCHK(lbmk::launch_reduce_state_f64(s->g, s->k, s->f<double>(s->fcur),
+                                             s->T<double>(s->tcur), s->p.C_v, s->n, out_dev,
+                                             s->stream));
+    else
+        HIPCHK(lbmk::launch_reduce_state_f32(s->g, s->k, s->f<float>(s->fcur), s->lo(s->fcur),
+                                             s->T<float>(s->tcur), s->p.C_v, s->n, out_dev,
+                                             s->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_health(lbm_sim* s, int64_t* nonfinite, int64_t* psi_clamps) {
     if (!s) return fail(LBM_EINVAL, "null sim");
     HIPCHK(hipSetDevice(s->dev));

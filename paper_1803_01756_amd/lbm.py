@@ -91,6 +91,7 @@ def lib():
             "lbm_eos_latent_heat": (C.c_int, [P, C.c_double, dp]),
             "lbm_eos_jacob": (C.c_int, [P, C.c_double, C.c_double, dp]),
             "lbm_health": (C.c_int, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+            "lbm_reduce_noalloc": (C.c_int, [vp, vp]),
             "lbm_pool_slot_health": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64),
                                                C.POINTER(C.c_int64)]),
             "lbm_workspace_bytes": (C.c_size_t, [P]),
@@ -139,7 +140,7 @@ def exported_symbols():
     return ["lbm_params_default", "lbm_params_resolve", "lbm_eos_critical", "lbm_eos_critical_cs",
             "lbm_eos_coexistence", "lbm_eos_pressure", "lbm_eos_latent_heat", "lbm_eos_jacob",
             "lbm_workspace_bytes", "lbm_create", "lbm_step",
-            "lbm_moments", "lbm_reduce", "lbm_synchronize",
+            "lbm_moments", "lbm_reduce", "lbm_reduce_noalloc", "lbm_synchronize",
             "lbm_health", "lbm_destroy",
             "lbm_time",
             "lbm_get_params", "lbm_last_error", "lbm_state_bytes", "lbm_save", "lbm_load",
@@ -253,6 +254,12 @@ def lbm_reduce(h: int, check: bool = True):
     if check or st != LBM_EUNSTABLE:
         _check(st)
     return out
+
+
+def lbm_reduce_noalloc(h: int, out_dev: int):
+    """Enqueue the lbm_reduce totals into 5 doubles of device memory at
+    out_dev (allocation-free, asynchronous)."""
+    _check(lib().lbm_reduce_noalloc(C.c_void_p(h), C.c_void_p(out_dev)))
 
 
 def lbm_synchronize(h: int):
