@@ -92,7 +92,9 @@ enum {
                               p0 = P_EOS(rho_v, T_in); the boundary densities
                               are their vapour-branch roots.  Stencils past
                               the ends see the boundary column's own values;
-                              the inlet column holds T = T_in.              */
+                              the inlet column holds T = T_in, the outlet
+                              column T = T_out when T_out > 0 (else its T
+                              evolves).                                     */
     LBM_PHASE_PROPS = 128u, /* lambda and C_v interpolated between the gas
                               values (lambda, C_v) and the liquid values
                               (lambda_l, C_v_l) with the clamped fraction of
@@ -143,6 +145,21 @@ typedef struct {
     uint32_t flags;         /* LBM_FREEZE_T | LBM_SINGLE_PHASE | LBM_PERIODIC_Y |
                                LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS |
                                LBM_OPEN_X | LBM_PHASE_PROPS | LBM_TOP_MIXED      */
+    double alpha_max;       /* > 0: a stated departure from Eq. 17 at delta t = 1.
+                               The explicit RK4 of the conduction term with the
+                               nine-point Laplacian is stable only while the
+                               diffusivity lambda / (rho C_v) stays below 0.522;
+                               vapour in equilibrium with liquid below ~0.74 T_c
+                               is thinner than that allows at lambda = 0.25,
+                               C_v = 5.  With alpha_max > 0 the conduction term
+                               of a node whose diffusivity exceeds alpha_max is
+                               scaled by alpha_max / (lambda / (rho C_v)), so it
+                               acts with diffusivity alpha_max there; 0: off
+                               (the paper's equation).  Must be 0 or in
+                               (0, 0.522].                                      */
+    double T_out;           /* LBM_OPEN_X outlet temperature: > 0 held (a
+                               reservoir of vapour at T_out); 0: the outlet
+                               column's T evolves                               */
 } lbm_params;
 
 /* Fill *p with the defaults: Nx = 128, Ny = 32, a = 3/49, b = 2/21, R = 1,

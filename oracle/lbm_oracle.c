@@ -62,8 +62,11 @@
  *    are rebuilt from the known ones at the start of each step (time level
  *    n).  Stencils that reach past x = 0 or x = Nx-1 see a zero-gradient
  *    ghost (the boundary column's own psi, T, u).  The inlet column holds
- *    T = T_in; the outlet's T evolves.  With Tw_end > 0 the plates'
- *    temperature varies linearly from Tw at x = 0 to Tw_end at x = Nx-1.
+ *    T = T_in; the outlet column holds T = T_out when T_out > 0 (the outlet
+ *    opens onto saturated vapour, which the paper has entering through it
+ *    when the flow reverses), else its T evolves.  With Tw_end > 0 the
+ *    plates' temperature varies linearly from Tw at x = 0 to Tw_end at
+ *    x = Nx-1.
  *  - Phase-dependent conductivity and heat capacity (flag PHASE_PROPS; the
  *    paper keeps them equal in both phases): lambda(rho) and C_v(rho) are
  *    interpolated between the gas and liquid values with the clamped
@@ -71,6 +74,15 @@
  *    [lambda lap T + grad(lambda) . grad(T)] / (rho C_v), grad(lambda) by
  *    the same nine-point stencil on lambda(rho(n)); solid nodes carry the
  *    gas values.
+ *  - Departure from Eq. 17 at delta t = 1 (parameter alpha_max > 0, off by
+ *    default): the explicit RK4 of the conduction term with the nine-point
+ *    Laplacian is stable only while lambda / (rho C_v) <= 0.522; vapour in
+ *    equilibrium with liquid below ~0.73 T_c is thinner than that allows at
+ *    lambda = 0.25, C_v = 5 (the paper's values), which the Sec. 3.3 plates
+ *    reach (0.56 T_c at the outlet).  With alpha_max set, the conduction term
+ *    of a node whose diffusivity alpha = lambda / (rho C_v) exceeds alpha_max
+ *    is multiplied by alpha_max / alpha (it acts with diffusivity
+ *    alpha_max); everything else is unchanged.
  *  - Sec. 3.2 plates (flag TOP_MIXED; Fig. 4 is not available): the top
  *    plate holds T_w on the columns cold_x0 <= x < cold_x1 (the cold centre)
  *    and is adiabatic elsewhere; the bottom plate holds Tw_bot.  Adiabatic
@@ -132,6 +144,8 @@ typedef struct {
     int32_t cold_x0, cold_x1;     /* TOP_MIXED cold columns of the top plate */
     uint32_t flags;
     int32_t pad_;
+    double alpha_max;             /* > 0: cap of the thermal diffusivity lambda/(rho C_v) */
+    double T_out;                 /* OPEN_X outlet temperature: > 0 held; 0: evolves */
 } orc_params;
 
 /* ---- D2Q9 lattice, Eq. 2 (velocity index i = 0..8) ---------------------- */
@@ -465,6 +479,7 @@ static int on_frame(const orc_params* p, int x, int y) {
 static int t_held(const orc_params* p, int x, int y) {
     if (is_solid(p, y)) return 1;
     if ((p->flags & ORC_OPEN_X) && x == 0) return 1;
+    if ((p->flags & ORC_OPEN_X) && x == p->Nx - 1 && p->T_out > 0.0) return 1;
     return (p->flags & ORC_FRAME_T) && on_frame(p, x, y);
 }
 /* reservoir nodes of a FRAME_RHO frame */
@@ -548,6 +563,8 @@ void orc_sim_init(orc_sim* s, const double* rho0, double rho_uniform) {
             for (int i = 0; i < 9; ++i) s->f[FIDX(p, i, x, y)] = is_solid(p, y) ? 0.0 : feq[i];
             double Tb = is_solid(p, y) ? t_plate(p, x, y) : p->Tw;
             if ((p->flags & ORC_OPEN_X) && x == 0 && !is_solid(p, y)) Tb = t_inlet(p);
+            if ((p->flags & ORC_OPEN_X) && x == p->Nx - 1 && p->T_out > 0.0 && !is_solid(p, y))
+                Tb = p->T_out;
             s->T[IDX(p, x, y)] = t_held(p, x, y) ? Tb : p->T0;
         }
 }
@@ -736,9 +753,16 @@ static void heat_rhs(const orc_sim* s, const double* Ts, double* out) {
                 div += w * (EX[i] * uxn + EY[i] * uyn);
             }
             double r = s->rho[c], T = Ts[c], cv = cv_at(p, r);
-            double cond = (p->flags & ORC_PHASE_PROPS) ? lam_at(p, s, x, y) * lap + lx * tx + ly * ty
+            double lam_c = (p->flags & ORC_PHASE_PROPS) ? lam_at(p, s, x, y) : p->lambda;
+            double cond = (p->flags & ORC_PHASE_PROPS) ? lam_c * lap + lx * tx + ly * ty
                                                        : p->lambda * lap;
-            out[c] = -(s->ux[c] * tx + s->uy[c] * ty) + cond / (r * cv) -
+            double cond_term = cond / (r * cv);
+            /* departure (alpha_max > 0): the conduction term scaled down
+             * where the diffusivity alpha = lambda / (rho C_v) exceeds the
+             * cap, so that it acts with diffusivity alpha_max there */
+            double alpha = lam_c / (r * cv);
+            if (p->alpha_max > 0.0 && alpha > p->alpha_max) cond_term *= p->alpha_max / alpha;
+            out[c] = -(s->ux[c] * tx + s->uy[c] * ty) + cond_term -
                      T / (r * cv) * orc_dpdT(p, r, T) * div;
         }
 }

@@ -68,6 +68,7 @@ class OrcParams(C.Structure):
         ("lam_l", C.c_double), ("Cv_l", C.c_double),
         ("Tw_bot", C.c_double), ("cold_x0", C.c_int32), ("cold_x1", C.c_int32),
         ("flags", C.c_uint32), ("pad_", C.c_int32),
+        ("alpha_max", C.c_double), ("T_out", C.c_double),
     ]
 
 

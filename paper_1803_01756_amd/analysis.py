@@ -48,6 +48,24 @@ def liquid_sets(rho: np.ndarray, threshold: float):
     return out
 
 
+def liquid_sets_open(rho: np.ndarray, threshold: float):
+    """Connected liquid sets (4-neighbour, rho > threshold) of a field
+    rho[y, x] with plate rows and open (not periodic) x ends, largest first,
+    each as [node count, centroid y, centroid x, reaches the row below the
+    top plate, reaches the row above the bottom plate]."""
+    ny, nx = rho.shape
+    liq = rho > threshold
+    liq[0] = liq[-1] = False
+    lab, n = ndimage.label(liq)
+    out = []
+    for i in range(1, n + 1):
+        ys, xs = np.nonzero(lab == i)
+        out.append([int(ys.size), float(ys.mean()), float(xs.mean()), int(ys.max() == ny - 2),
+                    int(ys.min() == 1)])
+    out.sort(key=lambda r: -r[0])
+    return out
+
+
 def droplets(rho: np.ndarray, threshold: float):
     """Droplets touching each plate of a channel field rho[y, x] (plate rows
     included, periodic in x): connected sets (4-neighbour) of fluid nodes with

@@ -138,15 +138,20 @@ def open_channel(Nx: int = 1600, Ny: int = 48, contact_angle: float = 137.82,
     oscillating inlet pressure p0 (1 + 0.1 sin(2 pi n / p_period)) against a
     constant outlet pressure p0 (Zou-He ends, flag OPEN_X); plates at a
     temperature falling linearly from 0.86 T_c at the inlet to 0.56 T_c at the
-    outlet; inlet vapour at T_sat = 0.86 T_c; gravity g_x = 1e-4 along +x; the
-    paper's hydrophobic plates (137.82 degrees).  The oscillation frequency is
-    not given, so p_period is a parameter."""
+    outlet; inlet vapour at T_sat = 0.86 T_c and the outlet open onto the
+    same saturated vapour (T_out = T_sat: the paper has saturated vapour
+    entering through the exit when the flow reverses); gravity g_x = 1e-4
+    along +x; the paper's hydrophobic plates (137.82 degrees).  The
+    oscillation frequency is not given, so p_period is a parameter.  The
+    energy equation is the paper's unless alpha_max > 0 is passed (the
+    diffusivity cap, a departure for thin vapour)."""
     p = lbm.lbm_params_default(Nx=Nx, Ny=Ny, g_osc=0.0, period=0.0, precision=precision,
                                flags=lbm.LBM_OPEN_X)
     p = lbm.lbm_params_resolve(p)
     p.T_w = 0.86 * p.T_c
     p.T_w_end = 0.56 * p.T_c
     p.T_in = p.T_0
+    p.T_out = p.T_0
     p.p_amp, p.p_period, p.g_x = p_amp, p_period, g_x
     frac = wall_fraction_for_angle(contact_angle)
     p.G_w = p.G

@@ -45,6 +45,9 @@ struct Phys {
     double T_in_eos;                    // temperature of the boundary EOS pressures
     double rho_sp;                      // vapour spinodal density at T_in_eos (bracket)
     double dT_in;                       // inlet temperature - T_ref
+    double dT_out;                      // held outlet temperature - T_ref (hold_out)
+    int hold_out;                       // the outlet column holds its temperature
+    double alpha_max;                   // > 0: cap of lambda / (rho C_v) in the conduction term
     double dT_w_end;                    // plate temperature at x = Nx-1 - T_ref
     int wall_ramp;                      // plate temperature linear in x
     double lam_l, cv_l;                 // liquid conductivity and heat capacity

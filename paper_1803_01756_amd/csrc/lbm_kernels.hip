@@ -415,11 +415,14 @@ struct Coef {
 // 1/C_v (constants unless lambda and C_v depend on the phase).  The
 // conduction term [lambda lap T + grad(lambda).grad(T)] / (rho C_v) is
 // carried as q3 lap T plus a shift of the advecting velocity by
-// -grad(lambda) / (rho C_v).
+// -grad(lambda) / (rho C_v).  amax > 0: where the diffusivity
+// lambda / (rho C_v) exceeds amax the whole conduction term is scaled by
+// amax over it (a departure from Eq. 17 that keeps the explicit RK4 of the
+// conduction term inside its stability bound in thin vapour).
 template <class R>
 __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, R T_ref,
                                              const PhysR<R>& pc, bool cs, bool props,
-                                             R lam_c, R glx, R gly, R inv_cv) {
+                                             R lam_c, R glx, R gly, R inv_cv, R amax) {
     R A, r2D, c;
     if (cs) {
         // Carnahan-Starling: T (dP/dT)_rho = rho R Z(e) T, no sqrt(T) term
@@ -439,11 +442,17 @@ __device__ __forceinline__ Coef<R> heat_coef(R rho, R ux, R uy, R divu, R Tn, R 
         c = (props ? inv_cv : pc.inv_Cv) * omb * D * inv;
     }
     Coef<R> q;
-    q.ux = props ? ux - c * glx : ux;
-    q.uy = props ? uy - c * gly : uy;
+    const R lam = props ? lam_c : pc.lambda;
+    R cg = c;  // 1 / (rho C_v) as the conduction term sees it
+    q.q3 = c * lam;
+    if (amax > (R)0 && q.q3 > amax) {
+        cg = amax * rcp_r(lam);
+        q.q3 = amax;
+    }
+    q.ux = props ? ux - cg * glx : ux;
+    q.uy = props ? uy - cg * gly : uy;
     q.q1 = c * divu * (A - pc.rkB2 * r2D);
     q.q2 = c * divu * pc.rkB1 * r2D;
-    q.q3 = c * (props ? lam_c : pc.lambda);
     if (sizeof(R) == 4) {
         const R rs = (R)__builtin_amdgcn_rsqf((float)Tn);  // 1 / sqrt(T_n)
         const R sn = Tn * rs;
@@ -611,13 +620,15 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     auto on_frame = [&](const RowK& r) {
         return edge_col || (g.periodic_y && (r.sr == 0 || r.sr == g.rows - 1));
     };
-    // Open ends (OPEN_X): the inlet column holds T = T_in, stencils past the
-    // ends see the end column's own value (zero-gradient ghost), and the
-    // plates may carry a temperature linear in x.
+    // Open ends (OPEN_X): the inlet column holds T = T_in (the outlet column
+    // T = T_out when it is held), stencils past the ends see the end
+    // column's own value (zero-gradient ghost), and the plates may carry a
+    // temperature linear in x.
     const bool open_x = kExt && g.open_x != 0;
     const bool at_in = open_x && cx == 0, at_out = open_x && cx == g.Nx - 1;
+    const bool out_held = at_out && k.hold_out != 0;
     auto held = [&](const RowK& r) {
-        return (kExt && g.frame_t && on_frame(r)) || at_in;
+        return (kExt && g.frame_t && on_frame(r)) || at_in || out_held;
     };
     auto trix = [&](auto v) {
         if (!open_x) return tri(v);
@@ -928,7 +939,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                     inv_cv = rcp_r((R)(1.0 / k.inv_Cv) + (R)(k.cv_l - 1.0 / k.inv_Cv) * fr);
                 }
                 cf2 = heat_coef<R>(rhoP2, ux2.c, uy2.c, dv, T_ref + tn2.c, T_ref, cv, eos_cs,
-                                   props, lam_c, glx, gly, inv_cv);
+                                   props, lam_c, glx, gly, inv_cv, kExt ? (R)k.alpha_max : (R)0);
                 R h1 = heat_rhs<R>(tn3, tn2, tn1, cf2, T_ref);
                 if (held(rC)) h1 = 0;
                 acc2 = h1;
@@ -1307,10 +1318,14 @@ __global__ __launch_bounds__(256) void init_kernel(Grid g, Phys k, const double*
             f[q * g.plane + o] = (S)v;
         }
     }
-    // T = T_0 = T_ref, T_w on a held frame node, T_in on an open inlet
+    // T = T_0 = T_ref, T_w on a held frame node, T_in on an open inlet,
+    // T_out on a held open outlet
     const bool held = g.frame_t && (cx == 0 || cx == g.Nx - 1 ||
                                     (g.periodic_y && (y == 0 || y == g.Ny - 1)));
-    T[o] = (g.open_x && cx == 0) ? (S)k.dT_in : (held ? (S)k.dT_wall : (S)0);
+    T[o] = (g.open_x && cx == 0)
+               ? (S)k.dT_in
+               : ((g.open_x && k.hold_out && cx == g.Nx - 1) ? (S)k.dT_out
+                                                             : (held ? (S)k.dT_wall : (S)0));
 }
 
 // ---- deterministic FP64 reduction ------------------------------------------
@@ -1468,7 +1483,7 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
 }
 
 bool needs_ext(const Grid& g, const Phys& k) {
-    return g.frame_t || g.frame_rho || g.open_x || k.wall_ramp ||
+    return g.frame_t || g.frame_rho || g.open_x || k.wall_ramp || k.alpha_max > 0.0 ||
            (k.flags & (kEosCS | kPhaseProps | kTopMixed));
 }
 

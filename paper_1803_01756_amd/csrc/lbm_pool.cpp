@@ -346,7 +346,7 @@ lbm_status lbm_pool_run(lbm_pool* P, int32_t chunk) {
         SlotState& s = P->slots[act[j]];
         ext = ext || (s.p.flags & (LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS | LBM_OPEN_X |
                                    LBM_PHASE_PROPS | LBM_TOP_MIXED)) ||
-              s.p.T_w_end > 0.0;
+              s.p.T_w_end > 0.0 || s.p.alpha_max > 0.0;
         if (!s.ready_waited) {
             PCHK(hipStreamWaitEvent(P->main, s.ready, 0));
             s.ready_waited = true;

@@ -289,6 +289,10 @@ lbm_status validate(const lbm_params& p) {
         if (!(p0 * (1.0 + std::fabs(p.p_amp)) < pmax) || !(p0 * (1.0 - std::fabs(p.p_amp)) > 0.0))
             return fail(LBM_EINVAL, "LBM_OPEN_X: inlet pressure range leaves the vapour branch");
     }
+    if (!(p.alpha_max == 0.0 || (p.alpha_max > 0.0 && p.alpha_max <= 0.522)))
+        return fail(LBM_EINVAL, "alpha_max must be 0 (off) or in (0, 0.522]");
+    if (p.T_out != 0.0 && !((p.flags & LBM_OPEN_X) && p.T_out > 0.0))
+        return fail(LBM_EINVAL, "T_out must be 0, or positive with LBM_OPEN_X");
     if ((p.flags & LBM_FRAME_RHO) && !(p.rho_frame > 0.0))
         return fail(LBM_EINVAL, "LBM_FRAME_RHO needs rho_frame > 0");
     if (p.G == 0.0) return fail(LBM_EINVAL, "G must be nonzero");
@@ -321,6 +325,7 @@ lbm_status check_initial(const lbm_params& p, const double* rho0) {
             const bool frame = x == 0 || x == p.Nx - 1 || (per && (y == 0 || y == p.Ny - 1));
             double T = p.T_0;
             if ((p.flags & LBM_OPEN_X) && x == 0) T = T_in;
+            else if ((p.flags & LBM_OPEN_X) && x == p.Nx - 1 && p.T_out > 0.0) T = p.T_out;
             else if ((p.flags & LBM_FRAME_T) && frame) T = p.T_w;
             const double rr = ((p.flags & LBM_FRAME_RHO) && frame) ? p.rho_frame : r;
             const double arg = 2.0 * (E.P(rr, T) - rr / 3.0) / p.G;
@@ -450,6 +455,9 @@ void fill_phys(const lbm_params& p, Phys& k) {
         k.p_period = p.p_period;
     }
     k.dT_in = (p.T_in > 0.0 ? p.T_in : p.T_0) - p.T_0;
+    k.hold_out = (p.flags & LBM_OPEN_X) && p.T_out > 0.0 ? 1 : 0;
+    k.dT_out = k.hold_out ? p.T_out - p.T_0 : 0.0;
+    k.alpha_max = p.alpha_max > 0.0 ? p.alpha_max : 0.0;
     k.wall_ramp = p.T_w_end > 0.0 ? 1 : 0;
     k.lam_l = p.lambda_l;
     k.cv_l = p.C_v_l;
@@ -882,7 +890,7 @@ const char* lbm_last_error(void) { return g_err; }
 
 // Checkpoint magic; the number changes whenever the header (which holds
 // lbm_params) changes layout.
-constexpr char kCkptMagic[9] = "LBMCKPT3";
+constexpr char kCkptMagic[9] = "LBMCKPT4";
 
 size_t lbm_state_bytes(const lbm_sim* s) {
     return s ? sizeof(CkptHeader) + state_payload(s) : 0;

@@ -52,6 +52,7 @@ class lbm_params(C.Structure):
         ("lambda_l", C.c_double), ("C_v_l", C.c_double),
         ("T_w_bottom", C.c_double), ("cold_x0", C.c_int32), ("cold_x1", C.c_int32),
         ("precision", C.c_int32), ("flags", C.c_uint32),
+        ("alpha_max", C.c_double), ("T_out", C.c_double),
     ]
 
     def as_dict(self):

@@ -15,7 +15,8 @@ _MAP = dict(Nx="Nx", Ny="Ny", a="a", b="b", R="R", omega="omega", T_c="Tc", G="G
             g_osc="g_osc", period="period", g_x="gx", g_y="gy", rho_v="rho_v",
             rho_frame="rho_frame", p_amp="p_amp", p_period="p_period", T_w_end="Tw_end",
             T_in="T_in", lambda_l="lam_l", C_v_l="Cv_l", T_w_bottom="Tw_bot",
-            cold_x0="cold_x0", cold_x1="cold_x1", flags="flags")
+            cold_x0="cold_x0", cold_x1="cold_x1", flags="flags", alpha_max="alpha_max",
+            T_out="T_out")
 
 
 def to_oracle(orc, p):

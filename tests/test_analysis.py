@@ -61,3 +61,14 @@ def test_contact_flags():
     rho[6:9, 8] = 6.0    # under the top plate
     sets = sorted(analysis.liquid_sets(rho, 3.0), key=lambda r: r[1])
     assert [s[3:] for s in sets] == [[0, 1], [1, 0]]
+
+
+def test_open_sets_are_not_joined_across_the_ends():
+    rho = np.full((8, 20), 0.4)
+    rho[0] = rho[-1] = 0.0
+    rho[3:5, :3] = 6.0    # at the inlet
+    rho[5:7, -2:] = 6.0   # at the outlet, on the top plate (row 6 = ny - 2)
+    sets = analysis.liquid_sets_open(rho, 3.0)
+    assert [s[0] for s in sets] == [6, 4]
+    assert sets[0][1:] == [3.5, 1.0, 0, 0]
+    assert sets[1][1:] == [5.5, 18.5, 1, 0]

@@ -279,13 +279,17 @@ def test_cs_eos_parity(orc, precision, flags):
 
 @pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 @pytest.mark.parametrize("Nx,Ny", [(60, 20), (131, 24)])
-def test_open_channel_parity(orc, precision, Nx, Ny):
+@pytest.mark.parametrize("outlet", ["held", "evolves"])
+def test_open_channel_parity(orc, precision, Nx, Ny, outlet):
     """Sec. 3.3 boundary set (OPEN_X): Zou-He oscillating-pressure inlet and
     constant-pressure outlet, plates at 0.86 -> 0.56 T_c along x, gravity
-    +x, hydrophobic plates; 200 steps against the oracle (the end columns and
-    the strips that touch them included)."""
-    _case("open channel %dx%d precision=%d, 200 steps" % (Nx, Ny, precision))
+    +x, hydrophobic plates, the outlet column held at T_sat (T_out) or
+    evolving; 200 steps against the oracle (the end columns and the strips
+    that touch them included)."""
+    _case("open channel %dx%d precision=%d outlet %s, 200 steps" % (Nx, Ny, precision, outlet))
     p = configs.open_channel(Nx, Ny, p_period=300.0, precision=precision)
+    if outlet == "evolves":
+        p.T_out = 0.0
     rho0 = configs.initial_density(p, seed=21)
     e = field_errors(_gpu(p, rho0, 200), _oracle(orc, p, rho0, 200), fluid_mask(Nx, Ny))
     print(e, flush=True)
@@ -331,6 +335,40 @@ def test_top_mixed_parity(orc, precision, Nx, Ny, band):
         p.flags |= lbm.LBM_FRAME_T
     rho0 = configs.initial_density(p, seed=Nx + Ny)
     e = field_errors(_gpu(p, rho0, 200), _oracle(orc, p, rho0, 200), fluid_mask(Nx, Ny))
+    print(e, flush=True)
+    tol = (1e-11, 1e-9, 1e-11) if precision == lbm.LBM_FP64 else (1e-5, 1e-5, 1e-5)
+    assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
+
+
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
+@pytest.mark.parametrize("case", ["open", "plain", "props"])
+def test_diffusivity_cap_parity(orc, precision, case):
+    """The diffusivity cap alpha_max (departure from Eq. 17 for thin vapour)
+    at 0.1, below the vapour's lambda / (rho C_v) = 0.13 at 0.86 T_c, so it
+    acts on every vapour node: the open channel (60 x 20, 200 steps), the
+    plain cold-plate channel (96 x 24, 200 steps: the cap alone selects the
+    build with the optional features) and a liquid layer with phase-dependent
+    lambda and C_v (80 x 32; 150 steps in FP64, 50 in FP32, as the
+    phase-property test), against the oracle."""
+    _case("diffusivity cap 0.1, %s, precision=%d" % (case, precision))
+    n = 200
+    if case == "open":
+        p = configs.open_channel(60, 20, p_period=300.0, precision=precision, alpha_max=0.1)
+        rho0 = configs.initial_density(p, seed=21)
+    elif case == "plain":
+        p = configs.channel_params(96, 24, 90.0, 0.78, 2e-5, 200.0, precision, 0, alpha_max=0.1)
+        rho0 = configs.initial_density(p, seed=22)
+    else:
+        p = configs.channel_params(80, 32, 90.0, 0.78, 2e-5, 200.0, precision,
+                                   lbm.LBM_PHASE_PROPS, lambda_l=0.6, C_v_l=3.0, alpha_max=0.1)
+        y = np.arange(32)[:, None] * np.ones((1, 80))
+        layer = 0.5 * (1 - np.tanh((y - 7.5) / 2.0))
+        rho0 = (p.rho_g + (p.rho_l - p.rho_g) * layer) * (1 + 0.01 * inputs.density_field(80, 32, 1.0, 0.5, 4))
+        n = 150 if precision == lbm.LBM_FP64 else 50
+    ref = _oracle(orc, p, rho0, n)
+    m = fluid_mask(p.Nx, p.Ny)
+    assert (p.lambda_ / (ref[0][m] * p.C_v) > 0.1).sum() > 100  # the cap acts
+    e = field_errors(_gpu(p, rho0, n), ref, m)
     print(e, flush=True)
     tol = (1e-11, 1e-9, 1e-11) if precision == lbm.LBM_FP64 else (1e-5, 1e-5, 1e-5)
     assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]

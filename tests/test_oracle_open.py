@@ -86,3 +86,32 @@ def test_linear_plate_and_inlet_temperature_held(orc):
     np.testing.assert_allclose(T[-1], ramp, rtol=1e-15)
     np.testing.assert_allclose(T[1:-1, 0], p.T_in, rtol=1e-15)
     assert np.abs(T[1:-1, -1] - p.T0).max() > 1e-6  # the outlet column evolves
+
+
+@pytest.mark.parametrize("hold", [True, False])
+def test_held_outlet_keeps_linear_profile(orc, hold):
+    """T_out > 0 holds the outlet column at T_out.  Vapour at rest (both ends
+    at p0, one phase) between plates carrying the same linear ramp from T_in
+    to T_out: the linear field is a fixed point of the nine-point conduction
+    term wherever both end columns are held, since every stencil then sees
+    the linear field itself.  With the outlet evolving (T_out = 0) the
+    zero-gradient ghost past it bends the profile next to it, which tells
+    the two readings apart."""
+    Nx, Ny = 24, 7
+    p, tc = _open(orc, Nx, Ny, flags=orc.SINGLE_PHASE)
+    p.p_amp = 0.0
+    Tin, Tout = 0.86 * tc, 0.70 * tc
+    p.Tw, p.Tw_end, p.T_in = Tin, Tout, Tin
+    p.T_out = Tout if hold else 0.0
+    s = orc.Sim(p, rho_uniform=p.rho_v)
+    lin = Tin + (Tout - Tin) * np.arange(Nx) / (Nx - 1)
+    s.set_T(np.broadcast_to(lin, (Ny, Nx)).copy())
+    s.step(30)
+    rho, ux, uy, T = s.moments()[:4]
+    fl = slice(1, -1)
+    assert np.abs(ux[fl]).max() < 1e-13 and np.abs(uy[fl]).max() < 1e-13
+    if hold:
+        np.testing.assert_allclose(T[fl, -1], Tout, rtol=1e-15)
+        np.testing.assert_allclose(T[fl], np.broadcast_to(lin, (Ny - 2, Nx)), rtol=1e-13)
+    else:
+        assert np.abs(T[fl, -1] - Tout).max() > 1e-4 * tc

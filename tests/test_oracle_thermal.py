@@ -10,6 +10,12 @@
   R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 per step, exactly up to rounding.
   The printed weights (h1 + h2 + h3 + h4)/6 of Eq. 17 would give
   1 + 2z/3 + ... and fail.
+* The diffusivity cap alpha_max (a departure from Eq. 17 at delta t = 1 for
+  vapour thinner than the RK4 bound allows): the conduction term is linear
+  in lambda, so the capped right-hand side is the uncapped one with its
+  conduction part scaled by min(1, alpha_max rho C_v / lambda) node by
+  node; on modes it turns R(z D) into R(z alpha_max), which decays where
+  the uncapped scheme grows.
 """
 import numpy as np
 import pytest
@@ -278,3 +284,69 @@ def test_rk4_stability_bound_on_checkerboard(orc, D):
     r = _rk4_factor(-16.0 * D / 3.0)
     np.testing.assert_allclose(T, p.T0 + eps * r ** 10 * mode, rtol=0, atol=1e-12 * p.T0)
     assert (abs(r) < 1) == (D < 0.522)
+
+
+@pytest.mark.parametrize("D,cap", [(1.0, 0.25), (11.7, 0.5)])
+@pytest.mark.parametrize("mode", ["checkerboard", "sine"])
+def test_diffusivity_cap_on_modes(orc, D, cap, mode):
+    """D = 11.7 is lambda / (rho C_v) of saturated vapour at 0.56 T_c with the
+    paper's lambda and C_v; uncapped, the checkerboard mode grows at both D
+    (|R| > 1), the longest sine mode at D = 11.7."""
+    Nx = Ny = 8
+    rho, Cv = 0.4, 5.0
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y | orc.SINGLE_PHASE,
+                           period=0.0, lam=D * rho * Cv, Cv=Cv)
+    p.alpha_max = cap
+    s = orc.Sim(p, rho_uniform=rho)
+    x, y = _grid(Nx, Ny)
+    if mode == "checkerboard":
+        f, ev = (-1.0) ** (x + y), -16.0 / 3.0
+    else:
+        k = 2 * np.pi / Nx
+        f, ev = np.sin(k * x), 2 * (np.cos(k) - 1)
+    eps = 1e-6 * p.T0
+    s.set_T(p.T0 + eps * f)
+    s.step(10)
+    T = s.moments()[3]
+    r = _rk4_factor(ev * cap)
+    np.testing.assert_allclose(T, p.T0 + eps * r ** 10 * f, rtol=0, atol=1e-12 * p.T0)
+    assert abs(r) < 1
+    if mode == "checkerboard":
+        assert abs(_rk4_factor(ev * D)) > 1
+
+
+@pytest.mark.parametrize("props", [False, True])
+def test_diffusivity_cap_scales_conduction_node_by_node(orc, props):
+    """K(T) with the cap against its decomposition: K with lambda = 0 (and
+    lambda_l = 0) is the advection and compression part, the rest is the
+    conduction part, which the cap scales by min(1, alpha_max / alpha) with
+    alpha = lambda(rho) / (rho C_v(rho)); densities from vapour to liquid put
+    alpha on both sides of the cap."""
+    Nx, Ny = 13, 9
+    p = orc.default_params(Nx=Nx, Ny=Ny, flags=orc.PERIODIC_Y, lam=0.25, Cv=5.0)
+    if props:
+        p.flags |= orc.PHASE_PROPS
+        p.lam_l, p.Cv_l = 0.6, 2.5
+    rng = np.random.default_rng(17)
+    rho = np.exp(rng.uniform(np.log(0.03), np.log(6.5), (Ny, Nx)))
+    ux, uy = rng.uniform(-0.05, 0.05, (2, Ny, Nx))
+    T = p.T0 * (1 + 0.01 * rng.uniform(-1, 1, (Ny, Nx)))
+    full = orc.heat_rhs(p, rho, ux, uy, T)
+    lam, lam_l = p.lam, p.lam_l
+    p.lam, p.lam_l = 0.0, 0.0
+    rest = orc.heat_rhs(p, rho, ux, uy, T)
+    p.lam, p.lam_l = lam, lam_l
+    if props:
+        fr = np.clip((rho - p.rho_g) / (p.rho_l - p.rho_g), 0, 1)
+        alpha = (lam + (lam_l - lam) * fr) / (rho * (p.Cv + (p.Cv_l - p.Cv) * fr))
+    else:
+        alpha = lam / (rho * p.Cv)
+    cap = 0.4
+    assert (alpha > cap).sum() > 5 and (alpha < cap).sum() > 5
+    p.alpha_max = cap
+    capped = orc.heat_rhs(p, rho, ux, uy, T)
+    expect = rest + (full - rest) * np.minimum(1.0, cap / alpha)
+    np.testing.assert_allclose(capped, expect, rtol=1e-12, atol=1e-14 * np.abs(full).max())
+    # a cap above every node's diffusivity changes nothing, bit for bit
+    p.alpha_max = 1.01 * alpha.max()
+    assert np.array_equal(orc.heat_rhs(p, rho, ux, uy, T), full)
