@@ -145,56 +145,115 @@ def oracle_mlups(p, rho0, steps, omp=False):
 
 
 def batch_and_serve(args):
-    """64 channels of uneven size in one pool vs the same channels run one
-    after another alone; then a Poisson stream of requests served with
-    continuous batching, under a cap that never binds and again under one
-    (256 MiB) that makes requests wait for admission."""
+    """64 channels of uneven size in one pool (launch policy autotuned, and
+    the default heuristic for reference) against the same channels run one
+    after another alone, each at its own autotuned shape; then a Poisson
+    stream of requests served with continuous batching (warm-up requests
+    first, the launch policy tuned on the live mix once they are admitted),
+    under a cap that never binds and again under one (256 MiB) that makes
+    requests wait for admission.  A seeded 10 % sample of the measured
+    requests is rerun alone at its full step count and compared bitwise."""
     import numpy as np
     from paper_1803_01756_amd import inputs, lbm, serve
     chans = [serve.channel_request(d, args.batch_steps)
              for d in inputs.sample_channels(64, seed=1803)]
     lups = sum(serve.lup(p, args.batch_steps) for p, _ in chans)
-    log("batched: 64 channels x %d steps (%.2e node updates)" % (args.batch_steps, lups))
-    tb, _ = serve.run_batch(chans, args.batch_steps, chunk=1000)
-    log("batched %.3f s; now the same channels one after another" % tb)
-    ta, _ = serve.run_alone(chans, args.batch_steps)
+    log("batched: 64 channels x %d steps (%.2e node updates), pool autotuned"
+        % (args.batch_steps, lups))
+    info = {}
+    tb, _ = serve.run_batch(chans, args.batch_steps, chunk=1000, tune_steps=4, info=info)
+    log("batched %.3f s (tuned %.3f ms/step); default launch policy next" % (tb, info["tuned_ms_per_step"]))
+    tb0, _ = serve.run_batch(chans, args.batch_steps, chunk=1000)
+    log("default policy %.3f s; now the same channels one after another, each autotuned" % tb0)
+    alone_shapes = []
+    ta, _ = serve.run_alone(chans, args.batch_steps, tune_steps=3, shapes=alone_shapes)
+    seg = [sr for sr, _ in info["shapes"]]
     batched = dict(channels=64, steps=args.batch_steps, node_updates=lups,
                    seconds=round(tb, 4), mlups=round(lups / tb / 1e6, 1),
                    sims_per_s=round(64 / tb, 3),
+                   launch="lbm_pool_autotune (per bucket of fluid rows)",
+                   tuned_ms_per_step=round(info["tuned_ms_per_step"], 4),
+                   waves_per_step=sum(w for _, w in info["shapes"]),
+                   seg_rows_min_median_max=[min(seg), int(np.median(seg)), max(seg)],
+                   default_policy_seconds=round(tb0, 4),
+                   default_policy_mlups=round(lups / tb0 / 1e6, 1),
                    alone_seconds=round(ta, 4), alone_mlups=round(lups / ta / 1e6, 1),
+                   alone_launch="lbm_autotune per channel",
                    speedup_vs_alone=round(ta / tb, 3))
-    n_warm = 10
-    reqs = serve.make_requests(args.serve_requests, args.serve_rate)
-    log("served: %d requests at %.0f/s (first %d are warm-up)" % (len(reqs), args.serve_rate,
-                                                                   n_warm))
-    pool = lbm.Pool(200 << 30)
-    serve.serve(reqs, pool, chunk=500)
-    pool.close()
-    meas = reqs[n_warm:]
-    st = serve.latency_stats(meas)
-    lu = sum(serve.lup(r.params, r.steps) for r in meas)
-    served = dict(requests=len(meas), warmup_requests=n_warm, rate_per_s=args.serve_rate,
-                  cap_bytes=200 << 30, chunk_steps=500,
-                  p50_latency_s=round(st["p50_s"], 4), p99_latency_s=round(st["p99_s"], 4),
-                  mean_latency_s=round(st["mean_s"], 4), sims_per_s=round(st["sims_per_s"], 3),
-                  mlups=round(lu / st["span_s"] / 1e6, 1))
-    log("served p50 %.3f s p99 %.3f s, %.2f sims/s" % (st["p50_s"], st["p99_s"], st["sims_per_s"]))
-    # the same stream under a cap that binds: requests wait for admission
+    log("batched: %s" % batched)
+
+    n_warm, n_meas = args.serve_warmup, args.serve_requests
+    rng = np.random.default_rng(1803)
+    sample = set((n_warm + rng.choice(n_meas, max(1, n_meas // 10), replace=False)).tolist())
+
+    def keep_sampled(r):
+        if r.rid not in sample:
+            r.result = None
+
+    def stream(cap, rate=None, warm=None, nmeas=None):
+        rate = args.serve_rate if rate is None else rate
+        warm = n_warm if warm is None else warm
+        nmeas = n_meas if nmeas is None else nmeas
+        reqs = serve.make_requests(warm + nmeas, rate)
+        pool = lbm.Pool(cap)
+        serve.serve(reqs, pool, chunk=500, on_done=keep_sampled, tune_after=warm)
+        pool.close()
+        meas = reqs[warm:]
+        st = serve.latency_stats(meas)
+        lat = np.array([r.finished - r.arrival for r in meas])
+        wait = np.array([r.admitted - r.arrival for r in meas])
+        lu = sum(serve.lup(r.params, r.steps) for r in meas)
+        arr_span = meas[-1].arrival - meas[0].arrival
+        fifths = [round(float(np.percentile(c, 50)), 3) for c in np.array_split(lat, 5)]
+        out = dict(p50_latency_s=round(st["p50_s"], 4), p99_latency_s=round(st["p99_s"], 4),
+                   mean_latency_s=round(st["mean_s"], 4),
+                   p50_latency_by_arrival_fifth_s=fifths,
+                   admission_wait_s=dict(mean=round(float(wait.mean()), 4),
+                                         p50=round(float(np.percentile(wait, 50)), 4),
+                                         p99=round(float(np.percentile(wait, 99)), 4),
+                                         max=round(float(wait.max()), 4)),
+                   sims_per_s=round(st["sims_per_s"], 3),
+                   mlups=round(lu / st["span_s"] / 1e6, 1),
+                   offered_mlups=round(lu / arr_span / 1e6, 1),
+                   errors=sum(1 for r in reqs if r.error))
+        return reqs, out
+
+    log("served: %d requests at %.0f/s (first %d are warm-up), cap 200 GB"
+        % (n_warm + n_meas, args.serve_rate, n_warm))
+    reqs, out = stream(200 << 30)
+    served = dict(requests=n_meas, warmup_requests=n_warm, rate_per_s=args.serve_rate,
+                  cap_bytes=200 << 30, chunk_steps=500, tuned_after_admissions=n_warm, **out)
+    log("served: %s" % out)
+    # the sampled results against the same requests run alone
+    same = 0
+    checked = sorted(sample)
+    for rid in checked:
+        r = reqs[rid]
+        s = lbm.Sim(r.params, r.rho0)
+        s.step(r.steps)
+        ref = s.moments()
+        s.close()
+        same += int(r.result is not None and all(np.array_equal(a, b) for a, b in zip(r.result, ref)))
+    served["checked_alone"] = dict(sampled=len(checked), bitwise_equal=same,
+                                   sample="seeded 10 % of the measured requests (numpy "
+                                          "default_rng(1803)), each rerun alone for its full "
+                                          "step count")
+    log("served: %d of %d sampled results bitwise equal to their runs alone" % (same, len(checked)))
     cap = 256 << 20
-    reqs = serve.make_requests(args.serve_requests, args.serve_rate)
     log("served again under a %d MiB cap" % (cap >> 20))
-    pool = lbm.Pool(cap)
-    serve.serve(reqs, pool, chunk=500)
-    pool.close()
-    meas = reqs[n_warm:]
-    st = serve.latency_stats(meas)
-    wait = np.array([r.admitted - r.arrival for r in meas])
-    served["capped"] = dict(cap_bytes=cap, p50_latency_s=round(st["p50_s"], 4),
-                            p99_latency_s=round(st["p99_s"], 4),
-                            mean_admission_wait_s=round(float(wait.mean()), 4),
-                            max_admission_wait_s=round(float(wait.max()), 4),
-                            sims_per_s=round(st["sims_per_s"], 3))
+    _, out = stream(cap)
+    served["capped"] = dict(cap_bytes=cap, **out)
     log("capped: %s" % served["capped"])
+    # below capacity: the offered load at the specified rate is just above
+    # what the pool sustains, so the latency there keeps creeping up; at a
+    # lower rate it is stationary
+    rate2 = args.serve_rate_steady
+    log("served below capacity: %d requests at %.0f/s (first %d are warm-up)"
+        % (args.serve_requests_steady + n_warm // 2, rate2, n_warm // 2))
+    _, out = stream(200 << 30, rate=rate2, warm=n_warm // 2, nmeas=args.serve_requests_steady)
+    served["below_capacity"] = dict(rate_per_s=rate2, requests=args.serve_requests_steady,
+                                    warmup_requests=n_warm // 2, cap_bytes=200 << 30, **out)
+    log("below capacity: %s" % served["below_capacity"])
     return batched, served
 
 
@@ -443,7 +502,12 @@ def main():
                     help="force the launch shape (rows per wave) instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served runs")
     ap.add_argument("--batch-steps", type=int, default=10000)
-    ap.add_argument("--serve-requests", type=int, default=110)
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="measured requests of the served stream (after the warm-up ones)")
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-rate-steady", type=float, default=16.0,
+                    help="rate of the below-capacity served stream")
+    ap.add_argument("--serve-requests-steady", type=int, default=500)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp32",
                     help="storage of the headline 8192x512 run (default fp32)")

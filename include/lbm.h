@@ -389,8 +389,29 @@ lbm_status lbm_pool_info(const lbm_pool* pool, int32_t* active, size_t* bytes_us
 /* Time level of a slot (after the work enqueued so far), -1 if no such slot. */
 int64_t lbm_pool_slot_time(const lbm_pool* pool, int32_t slot);
 
-/* Rows per wave of every slot's launch shape (<= 0: per-slot default). */
+/* Rows per wave of every slot's launch shape, capped at the slot's rows
+ * (<= 0: the per-slot default, segments of at least 14 rows sized toward
+ * one resident round of waves; this also drops a tuned policy). */
 lbm_status lbm_pool_set_launch(lbm_pool* pool, int32_t seg_rows);
+
+/* Time launch policies on the slots that have steps left (all admitted slots
+ * if none has) and keep the fastest for them and for later admissions.  A
+ * policy gives each bucket of fluid rows (up to 32, 64, 128, 256, more) a
+ * target segment height, from 8 rows to whole slots; each slot then uses
+ * segments of about that height, balanced over its rows.  The search times
+ * the default heuristic, one target for all buckets, then each bucket
+ * present in turn with the others fixed, steps_per_trial batched steps per
+ * policy (after two untimed ones).  The trials step copies of the slots'
+ * memory: states, counters and time levels are unchanged.  Blocks until the
+ * pool's work is done; needs device memory for the copies (LBM_ENOMEM if
+ * there is none, the policy then stays as it was).  best_ms (may be NULL)
+ * receives the time per batched step of the chosen policy.  The results of
+ * the steps do not depend on the policy (bitwise). */
+lbm_status lbm_pool_autotune(lbm_pool* pool, int32_t steps_per_trial, double* best_ms);
+
+/* Launch shape of a slot: rows per wave and waves per step. */
+lbm_status lbm_pool_slot_launch(const lbm_pool* pool, int32_t slot, int32_t* seg_rows,
+                                int32_t* waves);
 
 /* Wait for all work of the pool. */
 lbm_status lbm_pool_synchronize(lbm_pool* pool);

@@ -58,6 +58,24 @@ struct SlotState {
 // words per slot in the health-counter array: non-finite readings, clamps
 constexpr int kSlotStat = 2;
 
+// Buckets of fluid rows for the tuned launch shapes: up to 32, 64, 128, 256
+// rows, and more.
+constexpr int kRowBuckets = 5;
+int row_bucket(int rows) {
+    int b = 0;
+    while (b < kRowBuckets - 1 && rows > (32 << b)) ++b;
+    return b;
+}
+
+// Segments of about `target` rows, balanced over the slot's rows, with
+// seg + 10 (the recomputed halo rows) a multiple of the six-row unroll.
+int balanced_seg_rows(int rows, int target) {
+    const int segs = std::max(1, (rows + target - 1) / target);
+    int sr = (rows + segs - 1) / segs;
+    sr = sr + (6 - (sr + 10) % 6) % 6;
+    return std::min(sr, rows);
+}
+
 size_t slot_bytes(const lbmhost::Layout& L) {
     return 2 * lbmhost::align_up(9 * L.plane * 4) + 2 * lbmhost::align_up(L.plane * 4);
 }
@@ -71,6 +89,9 @@ struct lbm_pool {
     bool owns_main = false;
     std::vector<SlotState> slots;
     int seg_cap = 0;  // rows per wave in the batch (0: per-slot default)
+    // tuned segment heights per bucket of fluid rows (lbm_pool_autotune;
+    // 0: the default heuristic)
+    int seg_target[kRowBuckets] = {};
     // table of the batched kernel: device copy and two pinned host stagings
     lbmk::Slot* table_dev = nullptr;
     lbmk::Slot* table_host[2] = {nullptr, nullptr};
@@ -162,6 +183,8 @@ SlotState* get_slot(lbm_pool* P, int32_t id) {
 
 int seg_rows_for(const lbm_pool* P, const SlotState& s) {
     if (P->seg_cap > 0) return std::min(P->seg_cap, s.L.rows);
+    const int t = P->seg_target[row_bucket(s.L.rows)];
+    if (t > 0) return balanced_seg_rows(s.L.rows, t);
     // many channels share one launch, so each keeps segments of at least
     // 14 rows rather than aiming at a full round of waves by itself
     return lbmhost::default_seg_rows(s.p, s.L.rows, 14);
@@ -549,8 +572,155 @@ int64_t lbm_pool_slot_time(const lbm_pool* P, int32_t id) {
 lbm_status lbm_pool_set_launch(lbm_pool* P, int32_t seg_rows) {
     if (!P) return fail(LBM_EINVAL, "null pool");
     P->seg_cap = seg_rows > 0 ? seg_rows : 0;
+    if (seg_rows <= 0)
+        for (int& t : P->seg_target) t = 0;
     for (SlotState& s : P->slots)
         if (s.used) lbmhost::fill_grid(s.p, s.L, seg_rows_for(P, s), s.g);
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_slot_launch(const lbm_pool* P, int32_t id, int32_t* seg_rows,
+                                int32_t* waves) {
+    const SlotState* s = get_slot(const_cast<lbm_pool*>(P), id);
+    if (!s) return fail(LBM_EINVAL, "no slot %d", id);
+    if (seg_rows) *seg_rows = s->g.seg_rows;
+    if (waves) *waves = s->g.n_units;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_autotune(lbm_pool* P, int32_t steps_per_trial, double* best_ms) {
+    if (!P) return fail(LBM_EINVAL, "null pool");
+    if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
+    PCHK(hipSetDevice(P->dev));
+    // the slots of the next chunk (those with steps left; all slots if none has)
+    std::vector<int> act;
+    for (size_t i = 0; i < P->slots.size(); ++i)
+        if (P->slots[i].used && P->slots[i].steps_left > 0) act.push_back((int)i);
+    if (act.empty())
+        for (size_t i = 0; i < P->slots.size(); ++i)
+            if (P->slots[i].used) act.push_back((int)i);
+    if (act.empty()) return fail(LBM_EINVAL, "autotune needs admitted slots");
+    PCHK(hipStreamSynchronize(P->main));
+    PCHK(hipStreamSynchronize(P->aux));
+    // Trials run on copies of the slots' memory, so the slots' states,
+    // counters and time levels stay as they are.
+    size_t total = 0;
+    std::vector<size_t> at(act.size());
+    for (size_t j = 0; j < act.size(); ++j) {
+        at[j] = total;
+        total += lbmhost::align_up(P->slots[act[j]].bytes);
+    }
+    const size_t stat_at = total;
+    total += lbmhost::align_up(act.size() * kSlotStat * sizeof(unsigned long long));
+    const size_t tab_at = total;
+    total += act.size() * sizeof(lbmk::Slot);
+    char* shadow = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&shadow), total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_ENOMEM, "autotune: no room for the %zu-byte trial copy", total);
+    }
+    std::vector<lbmk::Slot> tab(act.size());
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipError_t e = hipSuccess;
+    for (size_t j = 0; j < act.size() && e == hipSuccess; ++j) {
+        const SlotState& s = P->slots[act[j]];
+        e = hipMemcpyAsync(shadow + at[j], s.mem, s.bytes, hipMemcpyDeviceToDevice, P->main);
+    }
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    bool ext = false;
+    int present[kRowBuckets] = {};
+    for (int id : act) {
+        const SlotState& s = P->slots[id];
+        ext = ext || (s.p.flags & (LBM_FRAME_T | LBM_FRAME_RHO | LBM_EOS_CS | LBM_OPEN_X |
+                                   LBM_PHASE_PROPS | LBM_TOP_MIXED)) ||
+              s.p.T_w_end > 0.0 || s.p.alpha_max > 0.0;
+        present[row_bucket(s.L.rows)] = 1;
+    }
+    // time one policy (segment-height target per bucket) over the copies
+    auto trial = [&](const int* target, double* ms_out) -> hipError_t {
+        int units = 0;
+        for (size_t j = 0; j < act.size(); ++j) {
+            const SlotState& s = P->slots[act[j]];
+            const int t = target[row_bucket(s.L.rows)];
+            lbmk::Slot& q = tab[j];
+            q.k = s.k;
+            lbmhost::fill_grid(s.p, s.L,
+                               t > 0 ? balanced_seg_rows(s.L.rows, t)
+                                     : lbmhost::default_seg_rows(s.p, s.L.rows, 14),
+                               q.g);
+            q.mem = shadow + at[j];
+            for (int c = 0; c < 2; ++c) {
+                q.off_f[c] = (unsigned)(reinterpret_cast<char*>(s.f[c]) - s.mem);
+                q.off_T[c] = (unsigned)(reinterpret_cast<char*>(s.T[c]) - s.mem);
+            }
+            q.span = q.off_T[1] + (unsigned)(s.L.plane * 4);
+            q.n0 = s.n;
+            q.cur_f = s.cur_f;
+            q.cur_T = s.cur_T;
+            q.steps_left = steps_per_trial + 2;
+            q.unit_begin = units;
+            q.stat = reinterpret_cast<unsigned long long*>(shadow + stat_at) + j * kSlotStat;
+            units += q.g.n_units;
+        }
+        auto* dtab = reinterpret_cast<lbmk::Slot*>(shadow + tab_at);
+        hipError_t r = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(lbmk::Slot),
+                                      hipMemcpyHostToDevice, P->main);
+        for (int i = 0; i < 2 && r == hipSuccess; ++i)
+            r = lbmk::launch_step_batched(dtab, (int)act.size(), units, i, ext, P->main);
+        if (r == hipSuccess) r = hipEventRecord(ev0, P->main);
+        for (int i = 0; i < steps_per_trial && r == hipSuccess; ++i)
+            r = lbmk::launch_step_batched(dtab, (int)act.size(), units, 2 + i, ext, P->main);
+        if (r == hipSuccess) r = hipEventRecord(ev1, P->main);
+        if (r == hipSuccess) r = hipEventSynchronize(ev1);
+        float ms = 0.0f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, ev0, ev1);
+        *ms_out = ms / steps_per_trial;
+        return r;
+    };
+    // Segment heights with seg + 10 a multiple of 6, from the default
+    // heuristic's 14 rows up to whole slots.  First one height for every
+    // bucket, then each bucket present in turn with the others fixed.
+    const int cands[] = {8, 14, 20, 26, 32, 38, 44, 56, 68, 80, 104, 128, 182, 254, 1 << 20};
+    int cur[kRowBuckets] = {};
+    double best = 1e300;
+    if (e == hipSuccess) e = trial(cur, &best);  // the default heuristic
+    int pick[kRowBuckets];
+    for (int c : cands) {
+        if (e != hipSuccess) break;
+        for (int& t : pick) t = c;
+        double ms = 0.0;
+        e = trial(pick, &ms);
+        if (e == hipSuccess && ms < best) {
+            best = ms;
+            std::copy(pick, pick + kRowBuckets, cur);
+        }
+    }
+    for (int b = 0; b < kRowBuckets && e == hipSuccess; ++b) {
+        if (!present[b]) continue;
+        std::copy(cur, cur + kRowBuckets, pick);
+        int keep = cur[b];
+        for (int c : cands) {
+            if (e != hipSuccess || c == keep) continue;
+            pick[b] = c;
+            double ms = 0.0;
+            e = trial(pick, &ms);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                cur[b] = c;
+            }
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(P->main);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipFree(shadow);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "pool autotune: %s", hipGetErrorString(e));
+    P->seg_cap = 0;
+    std::copy(cur, cur + kRowBuckets, P->seg_target);
+    for (SlotState& s : P->slots)
+        if (s.used) lbmhost::fill_grid(s.p, s.L, seg_rows_for(P, s), s.g);
+    if (best_ms) *best_ms = best;
     return LBM_OK;
 }
 

@@ -125,6 +125,9 @@ def lib():
                                         C.POINTER(C.c_size_t)]),
             "lbm_pool_slot_time": (C.c_int64, [vp, C.c_int32]),
             "lbm_pool_set_launch": (C.c_int, [vp, C.c_int32]),
+            "lbm_pool_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_double)]),
+            "lbm_pool_slot_launch": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32),
+                                               C.POINTER(C.c_int32)]),
             "lbm_pool_synchronize": (C.c_int, [vp]),
             "lbm_pool_wait": (C.c_int, [vp, C.c_int32]),
         }
@@ -150,6 +153,7 @@ def exported_symbols():
             "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_slot_health", "lbm_pool_release",
             "lbm_pool_destroy",
             "lbm_pool_info", "lbm_pool_slot_time", "lbm_pool_set_launch",
+            "lbm_pool_autotune", "lbm_pool_slot_launch",
             "lbm_pool_synchronize", "lbm_pool_wait"]
 
 
@@ -487,6 +491,20 @@ class Pool:
     def set_launch(self, seg_rows: int):
         """Rows per wave for every slot; <= 0: per-slot default."""
         _check(lib().lbm_pool_set_launch(C.c_void_p(self.h), int(seg_rows)))
+
+    def autotune(self, steps_per_trial: int = 10) -> float:
+        """lbm_pool_autotune: keep the fastest launch policy for the slots
+        with steps left; returns its time per batched step in ms."""
+        ms = C.c_double()
+        _check(lib().lbm_pool_autotune(C.c_void_p(self.h), int(steps_per_trial), C.byref(ms)))
+        return ms.value
+
+    def slot_launch(self, slot: int):
+        """(rows per wave, waves per step) of a slot."""
+        sr, w = C.c_int32(), C.c_int32()
+        _check(lib().lbm_pool_slot_launch(C.c_void_p(self.h), int(slot), C.byref(sr),
+                                          C.byref(w)))
+        return sr.value, w.value
 
     def synchronize(self):
         """Wait for every enqueued chunk."""

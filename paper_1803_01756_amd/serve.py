@@ -55,8 +55,12 @@ def lup(p, steps: int) -> int:
 
 
 def run_batch(channels, steps: int, chunk: int = 1000, cap_bytes: int = 200 << 30,
-              seg_rows: int = 0, keep_results: bool = False):
-    """Step every channel `steps` times in one pool; returns (seconds, results)."""
+              seg_rows: int = 0, keep_results: bool = False, tune_steps: int = 0,
+              info: dict = None):
+    """Step every channel `steps` times in one pool; returns (seconds, results).
+    tune_steps > 0: lbm_pool_autotune with that many steps per trial before
+    the timed run (untimed); `info` then receives the tuned time per step
+    and the slots' launch shapes."""
     pool = lbm.Pool(cap_bytes)
     if seg_rows:
         pool.set_launch(seg_rows)
@@ -66,6 +70,13 @@ def run_batch(channels, steps: int, chunk: int = 1000, cap_bytes: int = 200 << 3
         if s is None:
             raise RuntimeError("batch does not fit under the cap")
         slots.append(s)
+    if tune_steps > 0:
+        ms = pool.autotune(tune_steps)
+        if info is not None:
+            info["tuned_ms_per_step"] = ms
+            info["shapes"] = [pool.slot_launch(s) for s in slots]
+    elif info is not None:
+        info["shapes"] = [pool.slot_launch(s) for s in slots]
     pool.synchronize()
     t0 = time.perf_counter()
     left = steps
@@ -81,12 +92,19 @@ def run_batch(channels, steps: int, chunk: int = 1000, cap_bytes: int = 200 << 3
     return dt, res
 
 
-def run_alone(channels, steps: int, keep_results: bool = False):
-    """The same channels one after another with lbm_create/lbm_step."""
+def run_alone(channels, steps: int, keep_results: bool = False, tune_steps: int = 0,
+              shapes: list = None):
+    """The same channels one after another with lbm_create/lbm_step;
+    tune_steps > 0: each is autotuned first (lbm_autotune, untimed), and
+    `shapes` receives each one's (rows per wave, waves)."""
     total = 0.0
     res = []
     for p, rho0 in channels:
         s = lbm.Sim(p, rho0)
+        if tune_steps > 0:
+            s.autotune(tune_steps)
+        if shapes is not None:
+            shapes.append(s.launch())
         s.synchronize()
         t0 = time.perf_counter()
         s.step(steps)
@@ -99,13 +117,17 @@ def run_alone(channels, steps: int, keep_results: bool = False):
 
 
 def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.perf_counter,
-          sleep=time.sleep, on_done=None):
+          sleep=time.sleep, on_done=None, tune_after: int = 0, tune_steps: int = 4):
     """Continuous-batching loop.  ``requests`` sorted by arrival.  Returns the
-    requests with admission / finish times and results filled in."""
+    requests with admission / finish times and results filled in.
+    tune_after > 0: once that many requests have been admitted, the pool's
+    launch policy is tuned on the live mix (lbm_pool_autotune, tune_steps
+    per trial; it blocks until the enqueued chunks are done)."""
     t0 = clock()
     queue = collections.deque()
     by_slot = {}
-    i, finished = 0, 0
+    i, finished, admitted = 0, 0, 0
+    tuned = tune_after <= 0
     n = len(requests)
     while finished < n:
         now = clock() - t0
@@ -124,6 +146,10 @@ def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.per
             queue.popleft()
             r.slot, r.admitted = slot, clock() - t0
             by_slot[slot] = r
+            admitted += 1
+        if not tuned and admitted >= tune_after and by_slot:
+            pool.autotune(tune_steps)
+            tuned = True
         if by_slot:
             pool.run(chunk)
             pool.wait(max_pending)

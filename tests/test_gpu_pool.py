@@ -122,6 +122,49 @@ def test_sampled_batch_channels_match_oracle(orc):
         pool.close()
 
 
+def test_pool_autotune_leaves_states_and_results_unchanged():
+    """lbm_pool_autotune on a batch whose slots span every row bucket (fluid
+    rows 18 to 298) and carry an optional feature: the states, time levels
+    and counters are those before the call (the trials step copies), every
+    slot's shape follows the chosen policy (segments of about the bucket's
+    target, balanced over its rows, seg + 10 a multiple of 6), and the
+    finished results equal the runs alone bitwise."""
+    _case("pool autotune")
+    chans = [_chan(300, 20, 120.0, 0.80, 2e-6, 400.0, 1), _chan(140, 60, 150.0, 0.78, 5e-6, 300.0, 2),
+             _chan(700, 100, 100.0, 0.84, 1e-6, 700.0, 3), _chan(96, 200, 130.0, 0.80, 3e-6, 250.0, 4),
+             _chan(200, 300, 90.0, 0.80, 2e-6, 500.0, 5, lbm.LBM_PHASE_PROPS)]
+    chans[-1][0].lambda_l, chans[-1][0].C_v_l = 0.6, 3.0
+    steps = 120
+    pool = lbm.Pool(1 << 31)
+    slots = [pool.admit(p, r0, steps) for p, r0 in chans]
+    pool.run(40)
+    before = [pool.moments(sl, p.Nx, p.Ny) for sl, (p, _) in zip(slots, chans)]
+    health = [pool.slot_health(sl) for sl in slots]
+    shapes0 = [pool.slot_launch(sl) for sl in slots]
+    ms = pool.autotune(4)
+    assert ms > 0
+    shapes = [pool.slot_launch(sl) for sl in slots]
+    print(dict(ms=ms, before=shapes0, after=shapes), flush=True)
+    for sl, (p, r0), b, h in zip(slots, chans, before, health):
+        assert pool.slot_time(sl) == 40 and pool.slot_health(sl) == h
+        for x, y in zip(pool.moments(sl, p.Nx, p.Ny), b):
+            assert np.array_equal(x, y)
+    for (sr, waves), (p, _) in zip(shapes, chans):
+        rows = p.Ny - 2
+        assert 1 <= sr <= rows and (sr == rows or (sr + 10) % 6 == 0)
+        assert waves == -(-p.Nx // 54) * -(-rows // sr)
+    while True:
+        pool.run(50)
+        pool.wait(0)
+        if all(pool.slot_time(sl) == steps for sl in slots):
+            break
+    for sl, (p, r0) in zip(slots, chans):
+        got = pool.moments(sl, p.Nx, p.Ny)
+        for x, y in zip(got, _alone(p, r0, steps)):
+            assert np.array_equal(x, y)
+    pool.close()
+
+
 def test_pool_refuses_other_precisions():
     """Slots hold FP32 deviations only: FP64 and mass-exact requests are
     refused with LBM_EINVAL and leave the pool empty."""

@@ -71,6 +71,10 @@ class FakePool:
         self.used -= self.slots.pop(sid)["need"]
         self.free_ids.append(sid)
 
+    def autotune(self, steps):
+        self.tuned_with = len(self.admit_log)
+        return 1.0
+
 
 def _reqs(n, rate, sizes, steps, seed=0):
     rng = np.random.default_rng(seed)
@@ -154,3 +158,15 @@ def test_retired_request_returns_an_error_and_the_loop_goes_on():
     bad = [r for r in reqs if r.error]
     assert len(bad) == 1 and bad[0].result is None and "non-finite" in bad[0].error
     assert all(r.result == ("result", r.slot) for r in reqs if not r.error)
+
+
+def test_tuning_happens_once_after_the_warmup_admissions():
+    clock = FakeClock()
+    pool = FakePool(10 ** 9, clock)
+    reqs = _reqs(30, 50.0, [(64, 32), (128, 48)], [1000, 3000])
+    serve.serve(reqs, pool, chunk=500, clock=clock, sleep=clock.sleep, tune_after=10)
+    assert pool.tuned_with >= 10 and all(r.finished >= r.arrival for r in reqs)
+    pool2 = FakePool(10 ** 9, clock)
+    serve.serve(_reqs(5, 50.0, [(64, 32)], [1000]), pool2, chunk=500, clock=clock,
+                sleep=clock.sleep)
+    assert not hasattr(pool2, "tuned_with")
