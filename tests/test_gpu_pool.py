@@ -64,7 +64,9 @@ def test_pool_mixed_features_equal_alone():
     feature (Sec. 3.2 plates, phase-dependent properties, Carnahan-Starling,
     open ends, a held reservoir frame): a feature in any slot makes the whole
     batch run the kernel build with the optional features, and every slot,
-    the plain one included, still gives bitwise its result alone."""
+    the plain one included, still gives bitwise its result alone.  A second
+    batch holds a plain channel and one whose only option is the diffusivity
+    cap, which alone selects that build."""
     _case("pool with optional features")
     prec = lbm.LBM_FP32_DEV
     plain = _chan(200, 30, 110.0, 0.80, 2e-6, 300.0, 11)
@@ -93,6 +95,16 @@ def test_pool_mixed_features_equal_alone():
         got = pool.moments(s, p.Nx, p.Ny)
         ref = _alone(p, r0, n)
         for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+    pool.close()
+    capped = configs.channel_params(150, 28, 100.0, 0.78, 2e-5, 200.0, prec, 0, alpha_max=0.1)
+    chans = [_chan(170, 22, 120.0, 0.80, 2e-6, 300.0, 16), (capped, configs.initial_density(capped, 17))]
+    pool = lbm.Pool(1 << 30)
+    sl = [pool.admit(p, r0, 150) for p, r0 in chans]
+    pool.run(150)
+    pool.wait(0)
+    for (p, r0), s in zip(chans, sl):
+        for a, b in zip(pool.moments(s, p.Nx, p.Ny), _alone(p, r0, 150)):
             assert np.array_equal(a, b)
     pool.close()
 
