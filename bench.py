@@ -258,16 +258,25 @@ def batch_and_serve(args):
 
 
 def precision_study():
-    """2048x256 channels with contact angles 60/90/120 degrees (seeds 1-3):
-    FP32 deviation storage against the FP64 build on the GPU, per-field
+    """2048x256 channels with contact angles 60/90/120 degrees (seeds 1-3),
+    and a liquid-rich one (90 degrees, a liquid layer filling the lower 40 %
+    of the channel, seed 4): FP32 deviation storage (and, for the liquid
+    layer, mass-exact FP32) against the FP64 build on the GPU, per-field
     differences at steps 100, 1000 and 20000, and the throughput of both."""
     import torch
-    from paper_1803_01756_amd import analysis, configs, lbm
+    from paper_1803_01756_amd import analysis, configs, inputs, lbm
     out = {}
-    for seed, ca in ((1, 60.0), (2, 90.0), (3, 120.0)):
-        p32 = configs.single_gpu_channel(ca, lbm.LBM_FP32_DEV)
+    cases = [(1, 60.0, False, lbm.LBM_FP32_DEV), (2, 90.0, False, lbm.LBM_FP32_DEV),
+             (3, 120.0, False, lbm.LBM_FP32_DEV), (4, 90.0, True, lbm.LBM_FP32_DEV),
+             (4, 90.0, True, lbm.LBM_FP32_DEV_MASSEXACT)]
+    for seed, ca, liquid, prec in cases:
+        p32 = configs.single_gpu_channel(ca, prec)
         p64 = configs.single_gpu_channel(ca, lbm.LBM_FP64)
-        rho0 = configs.initial_density(p32, seed=seed)
+        if liquid:
+            rho0 = inputs.layer_field(p32.Nx, p32.Ny, p32.rho_g, p32.rho_l, 0.4 * p32.Ny, 2.0,
+                                      0.01, seed)
+        else:
+            rho0 = configs.initial_density(p32, seed=seed)
         a, b = lbm.Sim(p32, rho0), lbm.Sim(p64, rho0)
         a.autotune(5)
         b.autotune(5)
@@ -286,11 +295,15 @@ def precision_study():
             errs[str(target)] = {k: float("%.3e" % v) for k, v in
                                  analysis.field_differences(a.moments(), b.moments()).items()}
         fl = fluid_nodes(p32) * 20000
-        out["%g deg" % ca] = dict(errors_fp32_vs_fp64=errs, fp32_mlups=round(fl / t32 / 1e6, 1),
-                                  fp64_mlups=round(fl / t64 / 1e6, 1))
+        name = "%g deg" % ca
+        if liquid:
+            name += ", liquid layer 40 %%, %s" % ("mass-exact" if prec == lbm.LBM_FP32_DEV_MASSEXACT
+                                                 else "FP32 deviations")
+        out[name] = dict(errors_fp32_vs_fp64=errs, fp32_mlups=round(fl / t32 / 1e6, 1),
+                         fp64_mlups=round(fl / t64 / 1e6, 1))
         a.close()
         b.close()
-        log("precision study %g deg: %s" % (ca, errs))
+        log("precision study %s: %s" % (name, errs))
     return out
 
 

@@ -46,6 +46,16 @@ def density_field(Nx: int, Ny: int, rho_init: float, noise: float, seed: int) ->
     return rho_init * (1.0 + noise * (2.0 * u - 1.0))
 
 
+def layer_field(Nx: int, Ny: int, rho_lo: float, rho_hi: float, height: float,
+                width: float, noise: float, seed: int) -> np.ndarray:
+    """A layer on the lower plate: rho_hi up to row `height`, rho_lo above,
+    joined by a tanh profile of the given width, times (1 + noise (2U - 1))
+    with the counters of density_field.  float64 [Ny, Nx]."""
+    y = np.arange(Ny, dtype=np.float64)[:, None] * np.ones((1, Nx))
+    h = 0.5 * (1.0 - np.tanh((y - height) / width))
+    return (rho_lo + (rho_hi - rho_lo) * h) * density_field(Nx, Ny, 1.0, noise, seed)
+
+
 def sample_channels(n: int, seed: int = 1803):
     """Parameter draws of the batched workload: Nx log-uniform on [256, 4096],
     Ny uniform on the multiples of 16 in [32, 256], contact angle uniform on
