@@ -420,6 +420,25 @@ def open_channel_run(steps=10500, every=500, alpha_max=0.25):
             min_rho=round(float(rho[1:-1].min()), 4)))
     out["mlups"] = round(fluid_nodes(p) * s.n / dt_steps / 1e6, 1)
     s.close()
+    # the same run in FP64 storage: liquid nodes at the paper's marks, next
+    # to the FP32 run's, to show the timeline does not hinge on the storage
+    q = configs.open_channel(alpha_max=alpha_max, precision=lbm.LBM_FP64)
+    s = lbm.Sim(q, configs.initial_density(q, seed=1))
+    s.autotune(3)
+    fp64 = []
+    for mark in (2500, 5000, 8500, 10500):
+        if mark > steps:
+            break
+        s.step(mark - s.n)
+        try:
+            rho = s.moments()[0]
+        except lbm.LBMError:
+            fp64.append(dict(step=mark, diverged=True))
+            break
+        fp64.append(dict(step=mark, liquid_nodes=int((rho[1:-1] > thr).sum()),
+                         liquid_nodes_x_gt_1500=int((rho[1:-1, 1500:] > thr).sum())))
+    s.close()
+    out["fp64_check"] = fp64
     log("open channel 1600x48: %s" % out)
     return out
 

@@ -340,6 +340,24 @@ def test_top_mixed_parity(orc, precision, Nx, Ny, band):
     assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
 
 
+def test_open_channel_full_size_parity(orc):
+    """The Sec. 3.3 channel at its full 1600 x 48 with the bench's setting
+    (outlet held at T_sat, diffusivity cap 0.25), 300 steps, element by
+    element against the oracle (its OpenMP build) over the whole grid, in
+    FP64 and FP32 storage."""
+    _case("open channel 1600x48 full size, 300 steps")
+    p = configs.open_channel(precision=lbm.LBM_FP64, alpha_max=0.25)
+    rho0 = configs.initial_density(p, seed=1)
+    o = orc.Sim(to_oracle(orc, p), rho0, omp=True)
+    o.step(300)
+    ref = o.moments()
+    for precision, tol in ((lbm.LBM_FP64, (1e-11, 1e-9, 1e-11)), (lbm.LBM_FP32_DEV, (1e-5, 1e-5, 1e-5))):
+        p.precision = precision
+        e = field_errors(_gpu(p, rho0, 300), ref, fluid_mask(p.Nx, p.Ny))
+        print(precision, e, flush=True)
+        assert e["rho"] < tol[0] and e["u"] < tol[1] and e["T"] < tol[2]
+
+
 @pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 @pytest.mark.parametrize("case", ["open", "plain", "props"])
 def test_diffusivity_cap_parity(orc, precision, case):
