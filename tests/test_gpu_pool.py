@@ -148,6 +148,9 @@ def test_pool_autotune_leaves_states_and_results_unchanged():
     chans[-1][0].lambda_l, chans[-1][0].C_v_l = 0.6, 3.0
     steps = 120
     pool = lbm.Pool(1 << 31)
+    with pytest.raises(lbm.LBMError) as ei:  # nothing admitted: nothing to tune
+        pool.autotune(2)
+    assert ei.value.status == lbm.LBM_EINVAL
     slots = [pool.admit(p, r0, steps) for p, r0 in chans]
     pool.run(40)
     before = [pool.moments(sl, p.Nx, p.Ny) for sl, (p, _) in zip(slots, chans)]
