@@ -148,7 +148,11 @@ def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.per
             by_slot[slot] = r
             admitted += 1
         if not tuned and admitted >= tune_after and by_slot:
-            pool.autotune(tune_steps)
+            try:
+                pool.autotune(tune_steps)
+            except lbm.LBMError as e:  # no device memory for the trial copies:
+                if e.status != lbm.LBM_ENOMEM:  # keep the default policy
+                    raise
             tuned = True
         if by_slot:
             pool.run(chunk)

@@ -170,3 +170,14 @@ def test_tuning_happens_once_after_the_warmup_admissions():
     serve.serve(_reqs(5, 50.0, [(64, 32)], [1000]), pool2, chunk=500, clock=clock,
                 sleep=clock.sleep)
     assert not hasattr(pool2, "tuned_with")
+
+
+def test_tuning_without_memory_keeps_serving():
+    class NoRoomPool(FakePool):
+        def autotune(self, steps):
+            raise lbm.LBMError(lbm.LBM_ENOMEM, "no room for the trial copies")
+    clock = FakeClock()
+    pool = NoRoomPool(10 ** 9, clock)
+    reqs = _reqs(12, 50.0, [(64, 32)], [1000])
+    serve.serve(reqs, pool, chunk=500, clock=clock, sleep=clock.sleep, tune_after=4)
+    assert all(r.finished >= r.arrival and not r.error for r in reqs)
