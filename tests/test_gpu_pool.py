@@ -215,13 +215,15 @@ def test_pool_admission_by_footprint():
 
 
 def test_served_stream_results_equal_alone():
-    _case("served stream")
+    """A served stream whose launch policy is tuned on the live mix after
+    four admissions: every request's result equals its run alone."""
+    _case("served stream, tuned after 4 admissions")
     reqs = serve.make_requests(10, rate=40.0, steps_scale=0.02)
     pool = lbm.Pool(8 << 30)
-    serve.serve(reqs, pool, chunk=100)
+    serve.serve(reqs, pool, chunk=100, tune_after=4, tune_steps=2)
     pool.close()
-    assert all(r.finished > r.arrival for r in reqs)
-    for r in reqs[:3]:
+    assert all(r.finished > r.arrival and not r.error for r in reqs)
+    for r in reqs:
         ref = _alone(r.params, r.rho0, r.steps)
         for a, b in zip(r.result, ref):
             assert np.array_equal(a, b)
