@@ -228,6 +228,9 @@ bool coexistence(const Eos& E, double T, double* rg, double* rl, double* ps) {
 namespace lbmhost {
 
 bool make_layout(const lbm_params& p, Layout* L) {
+    // a grid whose step buffers fit the 32-bit offsets is far below these
+    // bounds; larger ones are refused before any index arithmetic
+    if (p.Nx < 1 || p.Ny < 1 || p.Nx > (1 << 28) || p.Ny > (1 << 28)) return false;
     const bool per = (p.flags & LBM_PERIODIC_Y) != 0;
     L->pitch = (p.Nx + 63) / 64 * 64;
     L->rows = per ? p.Ny : p.Ny - 2;

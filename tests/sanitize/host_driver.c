@@ -16,6 +16,8 @@
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <stddef.h>
+#include <stdint.h>
 #include <string.h>
 
 #include "lbm.h"
@@ -130,6 +132,55 @@ static void host_only(void) {
     EXPECT(lbm_pool_slot_time(NULL, 0) == -1);
 }
 
+/* Random parameter sets (a fixed xorshift sequence): every double field may
+ * become zero, negative, huge, infinite or NaN, every integer field an edge
+ * value; the host-only entry points must return a status or a size. */
+static uint64_t rng_state = 0x9e3779b97f4a7c15ull;
+static uint64_t next_u64(void) {
+    rng_state ^= rng_state << 13;
+    rng_state ^= rng_state >> 7;
+    rng_state ^= rng_state << 17;
+    return rng_state;
+}
+static void fuzz_params(int rounds) {
+    const double special[] = {0.0, -1.0, 1e300, -1e300, INFINITY, -INFINITY, NAN, 1e-300, 0.5, 2.0};
+    const int32_t ints[] = {0, -1, 1, 2, 3, 4, 5, 64, 1 << 20, INT32_MIN, INT32_MAX};
+    const lbm_params base = channel(96, 24, 0);
+    for (int r = 0; r < rounds; ++r) {
+        lbm_params p = base;
+        double* d = &p.a;  /* the doubles from a to rho_frame... are contiguous in groups */
+        (void)d;
+        unsigned char* raw = (unsigned char*)&p;
+        /* walk the struct field by field through known offsets */
+        const size_t dbl_first = offsetof(lbm_params, a), dbl_last = offsetof(lbm_params, T_w_bottom);
+        for (size_t o = dbl_first; o <= dbl_last; o += sizeof(double))
+            if (next_u64() % 8 == 0) {
+                double v = special[next_u64() % (sizeof(special) / sizeof(special[0]))];
+                memcpy(raw + o, &v, sizeof(v));
+            }
+        if (next_u64() % 8 == 0) p.Nx = ints[next_u64() % 11];
+        if (next_u64() % 8 == 0) p.Ny = ints[next_u64() % 11];
+        if (next_u64() % 8 == 0) p.cold_x0 = ints[next_u64() % 11];
+        if (next_u64() % 8 == 0) p.cold_x1 = ints[next_u64() % 11];
+        if (next_u64() % 8 == 0) p.precision = ints[next_u64() % 11];
+        if (next_u64() % 4 == 0) p.flags = (uint32_t)(next_u64() % 1024);
+        if (next_u64() % 8 == 0) p.alpha_max = special[next_u64() % 10];
+        if (next_u64() % 8 == 0) p.T_out = special[next_u64() % 10];
+        lbm_params q = p;
+        (void)lbm_params_resolve(&q);
+        const size_t ws = lbm_workspace_bytes(&p);
+        (void)lbm_pool_footprint(&p);
+        double g, l, ps, h;
+        (void)lbm_eos_coexistence(&p, base.T_0, &g, &l, &ps);
+        (void)lbm_eos_latent_heat(&p, base.T_0, &h);
+        if (ws > 0 && p.Nx <= 4096 && p.Ny <= 4096) {
+            lbm_sim* s = NULL;
+            const lbm_status st = lbm_create(&p, NULL, NULL, 0, NULL, &s);
+            if (st == LBM_OK) lbm_destroy(s);
+        }
+    }
+}
+
 static void with_gpu(void) {
     const uint32_t flag_sets[] = {0, LBM_PERIODIC_Y, LBM_OPEN_X, LBM_PHASE_PROPS, LBM_TOP_MIXED};
     for (size_t k = 0; k < sizeof(flag_sets) / sizeof(flag_sets[0]); ++k)
@@ -230,6 +281,7 @@ static void with_gpu(void) {
 
 int main(int argc, char** argv) {
     host_only();
+    fuzz_params(3000);
     if (argc > 1 && strcmp(argv[1], "gpu") == 0) with_gpu();
     printf("host sanitizer driver: %d failed expectations\n", failures);
     return failures != 0;
