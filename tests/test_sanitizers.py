@@ -44,32 +44,9 @@ def test_oracle_under_sanitizers(tmp_path, omp):
     assert rc == 0 and "0 non-finite" in out, out
 
 
-def build_sanitized_runtime(out_dir):
-    """The library with sanitizers on its host code, and the host driver
-    linked against it; returns the driver's path."""
-    from paper_1803_01756_amd import build as B
-    lib = os.path.join(out_dir, "liblbm_san.so")
-    srcs = [os.path.join(CSRC, s) for s in B.SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    host_san = []
-    for f in SAN[:-1]:
-        host_san += ["-Xarch_host", f]
-    cmd = [B.hipcc(), "--offload-arch=" + B.ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-mcode-object-version=5", "-ffp-contract=on",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Xarch_host", "-g"] + host_san + [
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", lib] + srcs
-    rc, out = _run(cmd)
-    assert rc == 0, out
-    exe = os.path.join(out_dir, "host_driver")
-    rc, out = _run([B.hipcc(), "-x", "c", "-O1"] + SAN + ["-I", os.path.join(ROOT, "include"),
-                   "-o", exe, os.path.join(HERE, "sanitize", "host_driver.c"), "-L", out_dir,
-                   "-llbm_san", "-Wl,-rpath," + out_dir, "-lm"])
-    assert rc == 0, out
-    return exe
-
-
 def test_runtime_host_code_under_sanitizers(tmp_path):
-    exe = build_sanitized_runtime(str(tmp_path))
+    from sanitize.build import build_runtime_driver
+    exe = build_runtime_driver(str(tmp_path))
     # the HIP runtime's own allocations are not ours to check for leaks
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:verify_asan_link_order=0")
     rc, out = _run([exe], env=env)
