@@ -161,7 +161,7 @@ def batch_and_serve(args):
     log("batched: 64 channels x %d steps (%.2e node updates), pool autotuned"
         % (args.batch_steps, lups))
     info = {}
-    tb, _ = serve.run_batch(chans, args.batch_steps, chunk=1000, tune_steps=4, info=info)
+    tb, _ = serve.run_batch(chans, args.batch_steps, chunk=1000, tune_steps=10, info=info)
     log("batched %.3f s (tuned %.3f ms/step); default launch policy next" % (tb, info["tuned_ms_per_step"]))
     tb0, _ = serve.run_batch(chans, args.batch_steps, chunk=1000)
     log("default policy %.3f s; now the same channels one after another, each autotuned" % tb0)
