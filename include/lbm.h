@@ -401,7 +401,8 @@ lbm_status lbm_pool_set_launch(lbm_pool* pool, int32_t seg_rows);
  * segments of about that height, balanced over its rows.  The search times
  * the default heuristic, one target for all buckets, then each bucket
  * present in turn with the others fixed, steps_per_trial batched steps per
- * policy (after two untimed ones).  The trials step copies of the slots'
+ * policy (after two untimed ones); the winner is kept only if it also beats
+ * the default heuristic over three times the steps, each timed twice.  The trials step copies of the slots'
  * memory: states, counters and time levels are unchanged.  Blocks until the
  * pool's work is done; needs device memory for the copies (LBM_ENOMEM if
  * there is none, the policy then stays as it was).  best_ms (may be NULL)

@@ -638,6 +638,7 @@ lbm_status lbm_pool_autotune(lbm_pool* P, int32_t steps_per_trial, double* best_
         present[row_bucket(s.L.rows)] = 1;
     }
     // time one policy (segment-height target per bucket) over the copies
+    int trial_steps = steps_per_trial;
     auto trial = [&](const int* target, double* ms_out) -> hipError_t {
         int units = 0;
         for (size_t j = 0; j < act.size(); ++j) {
@@ -658,7 +659,7 @@ lbm_status lbm_pool_autotune(lbm_pool* P, int32_t steps_per_trial, double* best_
             q.n0 = s.n;
             q.cur_f = s.cur_f;
             q.cur_T = s.cur_T;
-            q.steps_left = steps_per_trial + 2;
+            q.steps_left = trial_steps + 2;
             q.unit_begin = units;
             q.stat = reinterpret_cast<unsigned long long*>(shadow + stat_at) + j * kSlotStat;
             units += q.g.n_units;
@@ -669,13 +670,13 @@ lbm_status lbm_pool_autotune(lbm_pool* P, int32_t steps_per_trial, double* best_
         for (int i = 0; i < 2 && r == hipSuccess; ++i)
             r = lbmk::launch_step_batched(dtab, (int)act.size(), units, i, ext, P->main);
         if (r == hipSuccess) r = hipEventRecord(ev0, P->main);
-        for (int i = 0; i < steps_per_trial && r == hipSuccess; ++i)
+        for (int i = 0; i < trial_steps && r == hipSuccess; ++i)
             r = lbmk::launch_step_batched(dtab, (int)act.size(), units, 2 + i, ext, P->main);
         if (r == hipSuccess) r = hipEventRecord(ev1, P->main);
         if (r == hipSuccess) r = hipEventSynchronize(ev1);
         float ms = 0.0f;
         if (r == hipSuccess) r = hipEventElapsedTime(&ms, ev0, ev1);
-        *ms_out = ms / steps_per_trial;
+        *ms_out = ms / trial_steps;
         return r;
     };
     // Segment heights with seg + 10 a multiple of 6, from the default
@@ -709,6 +710,26 @@ lbm_status lbm_pool_autotune(lbm_pool* P, int32_t steps_per_trial, double* best_
                 best = ms;
                 cur[b] = c;
             }
+        }
+    }
+    // Short trials resolve differences of about a per cent: the chosen policy
+    // is kept only if it also beats the default heuristic over three times
+    // the steps, each timed twice.
+    bool tuned = false;
+    for (int b = 0; b < kRowBuckets; ++b) tuned = tuned || cur[b] != 0;
+    if (tuned && e == hipSuccess) {
+        const int zero[kRowBuckets] = {};
+        trial_steps = 3 * steps_per_trial;
+        double tc = 0.0, td = 0.0, ms = 0.0;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            e = trial(cur, &ms);
+            tc += ms;
+            if (e == hipSuccess) e = trial(zero, &ms);
+            td += ms;
+        }
+        if (e == hipSuccess) {
+            if (td <= tc) std::copy(zero, zero + kRowBuckets, cur);
+            best = 0.5 * std::min(tc, td);
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(P->main);
