@@ -18,12 +18,34 @@ interface, so it can be exercised on the CPU with a fake pool.
 from __future__ import annotations
 
 import collections
+import os
 import time
 from dataclasses import dataclass, field
 
 import numpy as np
 
 from . import configs, inputs, lbm
+
+
+class _Ranges:
+    """roctx ranges around the serving loop's phases (admission, chunk
+    enqueue, read-out, tuning) for rocprofv3 --marker-trace, enabled by the
+    environment variable LBM_ROCTX=1; otherwise every call is a no-op."""
+
+    def __init__(self):
+        self.lib = None
+        if os.environ.get("LBM_ROCTX") == "1":
+            import ctypes
+            self.lib = ctypes.CDLL("libroctx64.so")
+            self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+
+    def push(self, name: str):
+        if self.lib is not None:
+            self.lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self.lib is not None:
+            self.lib.roctxRangePop()
 
 
 @dataclass
@@ -123,6 +145,7 @@ def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.per
     tune_after > 0: once that many requests have been admitted, the pool's
     launch policy is tuned on the live mix (lbm_pool_autotune, tune_steps
     per trial; it blocks until the enqueued chunks are done)."""
+    rg = _Ranges()
     t0 = clock()
     queue = collections.deque()
     by_slot = {}
@@ -135,6 +158,7 @@ def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.per
             queue.append(requests[i])
             i += 1
         # admit in arrival order while the footprint fits
+        rg.push("serve: admit")
         while queue:
             r = queue[0]
             slot = pool.admit(r.params, r.rho0, r.steps)
@@ -147,19 +171,26 @@ def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.per
             r.slot, r.admitted = slot, clock() - t0
             by_slot[slot] = r
             admitted += 1
+        rg.pop()
         if not tuned and admitted >= tune_after and by_slot:
+            rg.push("serve: tune")
             try:
                 pool.autotune(tune_steps)
             except lbm.LBMError as e:  # no device memory for the trial copies:
                 if e.status != lbm.LBM_ENOMEM:  # keep the default policy
                     raise
+            rg.pop()
             tuned = True
         if by_slot:
+            rg.push("serve: chunk")
             pool.run(chunk)
             pool.wait(max_pending)
+            rg.pop()
         elif i < n:
             sleep(max(0.0, requests[i].arrival - (clock() - t0)))
         done = pool.poll()
+        if done:
+            rg.push("serve: read-out")
         for slot in done:
             r = by_slot.pop(slot)
             try:
@@ -173,6 +204,8 @@ def serve(requests, pool, chunk: int = 500, max_pending: int = 2, clock=time.per
             finished += 1
             if on_done:
                 on_done(r)
+        if done:
+            rg.pop()
         if by_slot and not done:
             sleep(0.0002)  # remaining slots are finishing their last chunk
     return requests

@@ -10,6 +10,8 @@
 * Non-finite states: lbm_synchronize, lbm_moments and lbm_reduce return
   LBM_EUNSTABLE once a step has read a non-finite rho or T; before that
   they return LBM_OK.
+* A NaN population injected through a checkpoint, and a drive far outside
+  the method's range, are reported the same way.
 * The pool retires a request whose state turns non-finite (no further
   steps, reported by lbm_pool_poll, LBM_EUNSTABLE from lbm_pool_moments)
   while the other requests of the same batch stay bitwise equal to their
@@ -169,3 +171,54 @@ def test_pool_refuses_density_without_real_psi():
         pool.admit(p, r0, 10)
     assert ei.value.status == lbm.LBM_EINVAL
     pool.close()
+
+
+@pytest.mark.parametrize("precision", [lbm.LBM_FP32_DEV, lbm.LBM_FP64])
+def test_nan_population_injected_via_load_is_reported(precision):
+    """A checkpoint whose state holds one NaN population (f_1 of one fluid
+    node, written into the saved bytes) loads, and the next step reports it:
+    lbm_synchronize returns LBM_EUNSTABLE and the health counters count the
+    non-finite readings.  The checkpoint holds a 16-byte header before the
+    parameters, then the nine population planes [9][rows][pitch] with the
+    plane stride pitch * rows + 832 elements."""
+    import ctypes as C
+    _case("NaN population injected via lbm_load, precision=%d" % precision)
+    p = configs.oracle_size_channel(precision)
+    s = lbm.Sim(p, configs.initial_density(p, seed=5))
+    s.step(10)
+    blob = bytearray(s.save())
+    esz = 8 if precision == lbm.LBM_FP64 else 4
+    pitch = -(-p.Nx // 64) * 64
+    plane = pitch * (p.Ny - 2) + 832
+    head = 16 + C.sizeof(lbm.lbm_params)
+    row, col = 7, 40
+    off = head + (1 * plane + row * pitch + col) * esz
+    nan = np.array([np.nan], dtype=np.float64 if esz == 8 else np.float32).tobytes()
+    blob[off:off + esz] = nan
+    s.load(bytes(blob))
+    assert s.health() == (0, 0)
+    s.step(1)
+    with pytest.raises(lbm.LBMError) as ei:
+        s.synchronize()
+    assert ei.value.status == lbm.LBM_EUNSTABLE
+    assert s.health()[0] >= 1
+    s.close()
+
+
+def test_large_gravity_diverges_and_is_reported(orc):
+    """A drive far outside the method's range (gravity 0.2 along x on the
+    64 x 24 channel) makes the state unsound within 40 steps in the oracle;
+    the GPU run reports it by step 60 through lbm_synchronize."""
+    _case("gravity 0.2: divergence reported")
+    p = configs.channel_params(64, 24, 90.0, 0.8, 2e-6, 200.0, lbm.LBM_FP32_DEV, 0, g_x=0.2)
+    rho0 = configs.initial_density(p, seed=3)
+    o = orc.Sim(to_oracle(orc, p), rho0)
+    o.step(40)
+    r = o.moments()[0][1:-1]
+    assert not (np.isfinite(r).all() and r.min() > 0)
+    s = lbm.Sim(p, rho0)
+    s.step(60)
+    with pytest.raises(lbm.LBMError) as ei:
+        s.synchronize()
+    assert ei.value.status == lbm.LBM_EUNSTABLE
+    s.close()
