@@ -36,7 +36,16 @@ class _Ranges:
         self.lib = None
         if os.environ.get("LBM_ROCTX") == "1":
             import ctypes
-            self.lib = ctypes.CDLL("libroctx64.so")
+            # the rocprofiler-sdk library is the one rocprofv3 traces; the
+            # older roctx library is the fallback
+            for name in ("librocprofiler-sdk-roctx.so.1", "libroctx64.so"):
+                try:
+                    self.lib = ctypes.CDLL(name)
+                    break
+                except OSError:
+                    continue
+            if self.lib is None:
+                raise OSError("LBM_ROCTX=1 but no roctx library could be loaded")
             self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
 
     def push(self, name: str):
