@@ -170,6 +170,9 @@ def batch_and_serve(args):
     seg = [sr for sr, _ in info["shapes"]]
     batched = dict(channels=64, steps=args.batch_steps, node_updates=lups,
                    seconds=round(tb, 4), mlups=round(lups / tb / 1e6, 1),
+                   hbm_gbs_algorithmic=round(lups / tb * BYTES_PER_LUP[lbm.LBM_FP32_DEV] / 1e9, 1),
+                   roofline_frac=round(lups / tb * BYTES_PER_LUP[lbm.LBM_FP32_DEV] / 1e9
+                                       / HBM_PEAK_GBS, 4),
                    sims_per_s=round(64 / tb, 3),
                    launch="lbm_pool_autotune (per bucket of fluid rows)",
                    tuned_ms_per_step=round(info["tuned_ms_per_step"], 4),
