@@ -306,9 +306,11 @@ lbm_status lbm_load(lbm_sim* sim, const void* host, size_t bytes);
 /* Launch shape of the fused step kernel: each wave owns a strip of 54
  * columns and marches over seg_rows fluid rows.  seg_rows <= 0 restores the
  * default: segments sized for about 3072 waves (one resident round at three
- * waves per SIMD on 256 CUs; 2048 and two waves for FP64), at least 2 rows, with seg_rows + 10 a multiple
- * of 6 (pool slots: at least 14 rows, see lbm_pool_set_launch).  lbm_autotune times candidate shapes instead.  The result of a step
- * does not depend on the shape (bitwise). */
+ * waves per SIMD on 256 CUs; 2048 and two waves for FP64 and mass-exact
+ * storage), at least 2 rows, with seg_rows + 10 a multiple of 6 (pool slots:
+ * at least 14 rows, see lbm_pool_set_launch).  lbm_autotune times candidate
+ * shapes instead.  The result of a step does not depend on the shape
+ * (bitwise). */
 lbm_status lbm_set_launch(lbm_sim* sim, int32_t seg_rows);
 lbm_status lbm_get_launch(const lbm_sim* sim, int32_t* seg_rows, int32_t* waves);
 

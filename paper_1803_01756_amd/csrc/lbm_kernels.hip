@@ -1058,13 +1058,15 @@ __device__ __forceinline__ int wave_in_block() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
-// The FP64 build has its own kernel: it needs about 256 registers and runs
-// one wave per SIMD, the FP32 builds fit three.
-// Register budgets: three waves per SIMD for the FP32 builds (168 VGPRs), two
-// for the FP64 build (256); the interior path would otherwise take a few
+// The FP64 build has its own kernel: it needs about 256 registers.
+// Register budgets: three waves per SIMD for the FP32 deviation build (168
+// VGPRs), two for the FP64 build (256) and for the mass-exact build, whose
+// FP64 density and split rest population need about 178 (held to 168 it
+// spills some 9 registers to scratch inside the row loop, which costs more
+// than the third wave gains); the interior path would otherwise take a few
 // more registers than that and lose a resident wave.
 template <class S, bool kMX, bool kExt>
-__global__ __launch_bounds__(kLanes* kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(kLanes* kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kMX ? 2 : 3)))
 void step_kernel(Grid g, Phys k, Bufs<S> B,
                                                                         long long n) {
     const int unit = unit_of_block(g.n_blocks_pad) * kWavesPerBlock + wave_in_block();

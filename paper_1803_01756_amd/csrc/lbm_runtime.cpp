@@ -387,9 +387,9 @@ namespace lbmhost {
 // segments of at least 16 rows so the 10 recomputed halo rows stay a minority.
 int default_seg_rows(const lbm_params& p, int rows, int min_rows) {
     const int strips = (p.Nx + lbmk::kOwned - 1) / lbmk::kOwned;
-    // one resident round: 256 CUs x 4 SIMDs x 3 waves for the FP32 builds,
-    // 2 waves for the FP64 build
-    const int want_units = p.precision == LBM_FP64 ? 2048 : 3072;
+    // one resident round: 256 CUs x 4 SIMDs x 3 waves for the FP32 deviation
+    // build, 2 waves for the FP64 and mass-exact builds
+    const int want_units = p.precision == LBM_FP32_DEV ? 3072 : 2048;
     int segs = std::max(1, (want_units + strips - 1) / strips);
     int sr = (rows + segs - 1) / segs;
     sr = std::max(sr, min_rows);
