@@ -611,6 +611,32 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     const unsigned xp = (unsigned)(cx == g.Nx - 1 ? 0 : cx + 1);
     const int own_w = min(kOwned, g.Nx - strip * kOwned);
     const bool own_lane = lane >= kHalo && lane < kHalo + own_w;
+    // Lanes that store post-collision populations (FP32 storage).  The
+    // collision is exact on every lane but the outermost one of each side
+    // (its force needs psi one column past the wave), so a wave holds its
+    // neighbours' first four columns exactly.  A boundary between two strips
+    // that would split a 64-byte chunk of a row into a part of at most four
+    // columns and the rest is moved so that one wave writes the whole chunk:
+    // a row store then makes fewer partial-chunk write requests, and every
+    // column is still written by exactly one wave.  Rows start on 64-byte
+    // boundaries.  T(n+1) is exact on the owned lanes only and keeps them.
+    // The FP64 build keeps the owned lanes: it is short of scalar registers,
+    // and a second lane mask live through its row loop costs more than the
+    // requests it saves.
+    const int c0 = strip * kOwned;
+    auto moved = [&](const int b, const int b_next) {
+        constexpr int cpc = 64 / (int)sizeof(S), kMove = kHalo - 1;
+        const int r = b % cpc;
+        if (r == 0) return b;
+        if (r <= kMove) return b - r;
+        if (cpc - r <= kMove && b + (cpc - r) <= b_next) return b + (cpc - r);
+        return b;
+    };
+    const int st_lo = strip > 0 ? moved(c0, c0 + own_w) : 0;
+    const int st_hi = strip + 1 < g.n_strips ? moved(c0 + kOwned, min(c0 + 2 * kOwned, g.Nx))
+                                             : c0 + own_w;
+    const bool store_lane = sizeof(S) == 8 ? own_lane
+                                           : c0 - kHalo + lane >= st_lo && c0 - kHalo + lane < st_hi;
     // The frame of a box: the outermost columns, and in a periodic box the
     // outermost rows.  FRAME_T holds its temperature (the RK right-hand
     // sides are zeroed there); FRAME_RHO makes it a reservoir at rest
@@ -890,12 +916,19 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                     for (int q = 0; q < 9; ++q)
                         dn[q] = (R)((q == 0 ? 4.0 / 9 : (q < 5 ? 1.0 / 9 : 1.0 / 36)) * dr);
                 }
-                if (own_lane) {
-                    // health of the owned node (state at level n): psi is 0
-                    // exactly when Eq. 10 was clamped (a NaN argument too)
+                // health of the owned node (state at level n): psi is 0
+                // exactly when Eq. 10 was clamped (a NaN argument too).  The
+                // FP32 builds count it in a block of its own (one lane mask
+                // there, the store mask below), the FP64 build beside its
+                // stores (the two masks are the same).
+                auto count_health = [&]() {
                     health += psi1.c == 0.0 ? 1u : 0u;
                     if (!(__builtin_isfinite(rho) && __builtin_isfinite(tn1.c)))
                         health |= 0x80000000u;
+                };
+                if (sizeof(S) == 4 && own_lane) count_health();
+                if (store_lane) {
+                    if (sizeof(S) == 8) count_health();
                     const unsigned so = B.fout + (unsigned)rB.sr * rowb;
                     if (kMX) {
                         // rest population takes whatever keeps sum_i d_i equal to
