@@ -799,6 +799,18 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
         issue_loads(ya - kHalo, raw);
         cur = raw;
     }
+    // row kr+1 into the registers of the next iteration
+    auto take_row = [&]() {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cur.d[q] = settle(raw.d[q]);
+        cur.T = settle(raw.T);
+        if (kMX) cur.lo = settle(raw.lo);
+    };
+    // Where the interior iteration takes its loaded row: just before the
+    // population stores in the plain FP32 build (measured faster there), just
+    // before the last stage otherwise (the mass-exact build measured slower
+    // with the early wait).
+    constexpr bool kEarlySettle = kAhead && !kMX;
     // A row iteration in two builds.  The general one (kFast false) handles
     // every case.  The interior one serves the steady state of a segment in
     // the common configuration (plates, temperature on, two phases, no
@@ -927,6 +939,12 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                         health |= 0x80000000u;
                 };
                 if (sizeof(S) == 4 && own_lane) count_health();
+                // The interior iteration of the plain FP32 build takes row kr+1
+                // into its registers here, before the stores: the wait for the
+                // loads then excludes these stores (one counter tracks both,
+                // and a store block under a lane mask makes the compiler's
+                // wait for the newest load a wait for everything issued).
+                if (kEarlySettle && kFast) take_row();
                 if (store_lane) {
                     if (sizeof(S) == 8) count_health();
                     const unsigned so = B.fout + (unsigned)rB.sr * rowb;
@@ -1008,12 +1026,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
             t3a = t3;
             // ------------- stage F: h4 and T(n+1) on row kr-5 -------------
         }
-        if (kAhead) {  // row kr+1 into the registers of the next iteration
-#pragma unroll
-            for (int q = 0; q < 9; ++q) cur.d[q] = settle(raw.d[q]);
-            cur.T = settle(raw.T);
-            if (kMX) cur.lo = settle(raw.lo);
-        }
+        if (kAhead && !(kEarlySettle && kFast)) take_row();
         if (kFast || !freezeT) {
             const RowK rF = kFast ? row_interior(kr, 5) : row_info(kr - 5, g);
             if (kFast || (rF.fluid && kr - 5 >= ya && kr - 5 < yb)) {

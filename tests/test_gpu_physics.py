@@ -40,7 +40,7 @@ def _oracle(orc, p, rho0, steps):
 
 
 @pytest.mark.parametrize("Nx,Ny", [(3, 4), (20, 5), (54, 6), (55, 7), (65, 9), (130, 12),
-                                   (109, 40)])
+                                   (109, 40), (112, 10), (433, 8)])
 def test_edge_grids_fp64(orc, Nx, Ny):
     _case("edge grid %dx%d fp64" % (Nx, Ny))
     p = configs.channel_params(Nx, Ny, 120.0, 0.8, 1e-5, 50.0, lbm.LBM_FP64)

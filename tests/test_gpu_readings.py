@@ -95,7 +95,7 @@ def test_eq3_rates_and_theta_off_default(orc, precision):
 
 
 @pytest.mark.parametrize("Nx,Ny", [(3, 4), (20, 5), (54, 6), (55, 7), (65, 9), (130, 12),
-                                   (109, 40)])
+                                   (109, 40), (112, 10), (433, 8)])
 @pytest.mark.parametrize("precision", [lbm.LBM_FP32_DEV, lbm.LBM_FP32_DEV_MASSEXACT])
 def test_edge_grids_fp32(orc, precision, Nx, Ny):
     """The edge grids in FP32 storage.  Next to the plates the adhesion force
@@ -104,7 +104,12 @@ def test_edge_grids_fp32(orc, precision, Nx, Ny):
     With the weak drive of the FP64 test (1e-5) a three-row channel moves
     at max |u| = 4e-4 and that floor alone is 2e-4 normwise; the drive here
     (5e-3, period 120) gives max |u| >= 0.03 on every grid (oracle), which
-    puts the floor near 3e-6, under the 1e-5 bar."""
+    puts the floor near 3e-6, under the 1e-5 bar.  Strips are 54 columns
+    wide and FP32 population stores move a boundary that would split a
+    64-byte chunk into four or fewer columns and the rest: 112 columns make
+    the first strip store all four columns of the second, 433 put boundaries
+    at every offset 6k mod 16 into a chunk (moved left, moved right, split,
+    aligned) and end on a one-column strip."""
     _case("edge grid %dx%d precision=%d" % (Nx, Ny, precision))
     p = configs.channel_params(Nx, Ny, 120.0, 0.8, 5e-3, 120.0, precision)
     rho0 = configs.initial_density(p, seed=Nx * 100 + Ny)
