@@ -767,13 +767,14 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     // seg_rows + 10 a multiple of 6 need no padding iterations.
     const int kr_end = yb + kHalo;
     // FP32 builds load row kr+1 at the top of iteration kr and move it into
-    // the registers stage A reads (cur) just before the last stage, so the
-    // loads overlap most of an iteration and the wait for them falls before
-    // the last store of the iteration rather than after it (one counter
-    // tracks both).  Every iteration loads: a row that is not a stored fluid
-    // row of the segment's range reads the first stored row instead (values
-    // never used).  The FP64 build (twice the registers per value) loads each
-    // row in stage A of its own iteration.
+    // the registers stage A reads (cur) later in the iteration (take_row
+    // below: before the population stores or before the last stage), so the
+    // loads overlap most of an iteration and the wait for them does not wait
+    // for the stores that follow it (one counter tracks both).  Every
+    // iteration loads: a row that is not a stored fluid row of the segment's
+    // range reads the first stored row instead (values never used).  The
+    // FP64 build (twice the registers per value) loads each row in stage A
+    // of its own iteration.
     constexpr bool kAhead = sizeof(S) == 4;
     struct RawRow {
         S d[9];
