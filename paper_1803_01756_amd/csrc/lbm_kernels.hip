@@ -611,18 +611,15 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     const unsigned xp = (unsigned)(cx == g.Nx - 1 ? 0 : cx + 1);
     const int own_w = min(kOwned, g.Nx - strip * kOwned);
     const bool own_lane = lane >= kHalo && lane < kHalo + own_w;
-    // Lanes that store post-collision populations (FP32 storage).  The
-    // collision is exact on every lane but the outermost one of each side
-    // (its force needs psi one column past the wave), so a wave holds its
-    // neighbours' first four columns exactly.  A boundary between two strips
-    // that would split a 64-byte chunk of a row into a part of at most four
-    // columns and the rest is moved so that one wave writes the whole chunk:
-    // a row store then makes fewer partial-chunk write requests, and every
-    // column is still written by exactly one wave.  Rows start on 64-byte
-    // boundaries.  T(n+1) is exact on the owned lanes only and keeps them.
-    // The FP64 build keeps the owned lanes: it is short of scalar registers,
-    // and a second lane mask live through its row loop costs more than the
-    // requests it saves.
+    // Lanes that store post-collision populations.  The collision is exact
+    // on every lane but the outermost one of each side (its force needs psi
+    // one column past the wave), so a wave holds its neighbours' first four
+    // columns exactly.  A boundary between two strips that would split a
+    // 64-byte chunk of a row into a part of at most four columns and the
+    // rest is moved so that one wave writes the whole chunk: a row store then
+    // makes fewer partial-chunk write requests, and every column is still
+    // written by exactly one wave.  Rows start on 64-byte boundaries.  T(n+1)
+    // is exact on the owned lanes only and keeps them.
     const int c0 = strip * kOwned;
     auto moved = [&](const int b, const int b_next) {
         constexpr int cpc = 64 / (int)sizeof(S), kMove = kHalo - 1;
@@ -635,8 +632,16 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
     const int st_lo = strip > 0 ? moved(c0, c0 + own_w) : 0;
     const int st_hi = strip + 1 < g.n_strips ? moved(c0 + kOwned, min(c0 + 2 * kOwned, g.Nx))
                                              : c0 + own_w;
-    const bool store_lane = sizeof(S) == 8 ? own_lane
-                                           : c0 - kHalo + lane >= st_lo && c0 - kHalo + lane < st_hi;
+    const bool store_lane = c0 - kHalo + lane >= st_lo && c0 - kHalo + lane < st_hi;
+    // Lane masks and the register budget (each choice measured on 8192 x
+    // 512): the FP64 and mass-exact builds count each node's health on the
+    // lanes that store it, beside the stores; the FP64 build, shortest of
+    // scalar registers, also tests the owned lanes only where T(n+1) is
+    // stored, so that a single mask stays live through its row loop.  The
+    // plain FP32 build counts health on the owned lanes in a block of its
+    // own.
+    constexpr bool kHealthOnStore = sizeof(S) == 8 || kMX;
+    constexpr bool kOwnedTestAtT = sizeof(S) == 8;
     // The frame of a box: the outermost columns, and in a periodic box the
     // outermost rows.  FRAME_T holds its temperature (the RK right-hand
     // sides are zeroed there); FRAME_RHO makes it a reservoir at rest
@@ -929,17 +934,14 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                     for (int q = 0; q < 9; ++q)
                         dn[q] = (R)((q == 0 ? 4.0 / 9 : (q < 5 ? 1.0 / 9 : 1.0 / 36)) * dr);
                 }
-                // health of the owned node (state at level n): psi is 0
-                // exactly when Eq. 10 was clamped (a NaN argument too).  The
-                // FP32 builds count it in a block of its own (one lane mask
-                // there, the store mask below), the FP64 build beside its
-                // stores (the two masks are the same).
+                // health of the node (state at level n): psi is 0 exactly
+                // when Eq. 10 was clamped (a NaN argument too)
                 auto count_health = [&]() {
                     health += psi1.c == 0.0 ? 1u : 0u;
                     if (!(__builtin_isfinite(rho) && __builtin_isfinite(tn1.c)))
                         health |= 0x80000000u;
                 };
-                if (sizeof(S) == 4 && own_lane) count_health();
+                if (!kHealthOnStore && own_lane) count_health();
                 // The interior iteration of the plain FP32 build takes row kr+1
                 // into its registers here, before the stores: the wait for the
                 // loads then excludes these stores (one counter tracks both,
@@ -947,7 +949,7 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 // wait for the newest load a wait for everything issued).
                 if (kEarlySettle && kFast) take_row();
                 if (store_lane) {
-                    if (sizeof(S) == 8) count_health();
+                    if (kHealthOnStore) count_health();
                     const unsigned so = B.fout + (unsigned)rB.sr * rowb;
                     if (kMX) {
                         // rest population takes whatever keeps sum_i d_i equal to
@@ -1034,7 +1036,17 @@ __device__ __forceinline__ void step_unit(const Grid& g, const Phys& k, const Bu
                 R h4 = heat_rhs<R>(t3c, t3b, t3a, cf5, T_ref);
                 if (held(rF)) h4 = 0;
                 const R tnew = tn5 + (acc5 + h4) * ((R)1 / 6);
-                if (own_lane) bstore((S)tnew, rb, vx, B.Tout + (unsigned)rF.sr * rowb);
+                if (kOwnedTestAtT) {
+                    // the owned-lane test is made here: the empty asm keeps
+                    // the compiler from hoisting it out of the loop as a
+                    // second live mask
+                    int ln = lane;
+                    asm volatile("" : "+v"(ln));
+                    if (ln >= kHalo && ln < kHalo + own_w)
+                        bstore((S)tnew, rb, vx, B.Tout + (unsigned)rF.sr * rowb);
+                } else if (own_lane) {
+                    bstore((S)tnew, rb, vx, B.Tout + (unsigned)rF.sr * rowb);
+                }
             }
         }
 
