@@ -9,7 +9,8 @@ and period 4000 steps, saturated vapour with +-1 % seeded noise.  It is the
 HBM-bound configuration: its 2 x 36 B populations + 2 x 4 B temperature per
 node (352 MB) exceed the 256 MB Infinity Cache.  One step = one launch of the
 fused kernel over the whole channel.  Inputs are resident in HBM before the
-timed region starts.
+timed region starts.  After tuning the launch shape the channel runs 0.1 s of
+untimed steps, then the W warm-up steps, then the K timed steps.
 
 Prints one JSON line.  `value` is MLUPS (million fluid-node updates per
 second).  `roofline` compares the algorithmic bytes of one launch (80 B per
